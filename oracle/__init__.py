@@ -1,0 +1,296 @@
+"""Plain FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It shares no code with the GPU library; the two meet only in the
+seeded input generators of ``paper_1507_06565_amd.workloads``.
+
+The heavy loops live in ``lbm_oracle.c`` (plain C, binary64, OpenMP over
+z-planes); this module marshals numpy arrays and adds the plain reductions of
+the paper's post-processing (planar averages, Darcy permeability, eq. (1)).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+BC = {"sbb": 0, "cli": 1, "bouzidi": 2}
+FLUID, SPHERE, WALL = 0, 1, 2
+SURF_SPHERE, SURF_WALL_LO, SURF_WALL_HI = 0, 1, 2
+
+
+class _ODomain(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3), ("wall_lo", C.c_int32 * 3),
+                ("wall_hi", C.c_int32 * 3), ("wall_hi_vel", C.c_double * 3),
+                ("spheres", C.POINTER(C.c_double)), ("nsph", C.c_int64), ("bc", C.c_int32)]
+
+
+class _OParams(C.Structure):
+    _fields_ = [("trt", C.c_int32), ("tau_plus", C.c_double), ("magic_lambda", C.c_double),
+                ("rho0", C.c_double), ("force", C.c_double * 3)]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "_liboracle.so")
+        src = os.path.join(_HERE, "lbm_oracle.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            _build.build()
+        L = C.CDLL(path)
+        P = C.POINTER
+        L.orc_flags.argtypes = [P(_ODomain), C.c_void_p]
+        L.orc_flags_bruteforce.argtypes = [P(_ODomain), C.c_void_p]
+        L.orc_count_links.argtypes = [P(_ODomain), C.c_void_p]
+        L.orc_count_links.restype = C.c_int64
+        L.orc_links.argtypes = [P(_ODomain), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p]
+        L.orc_entry_bisect.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, C.c_int]
+        L.orc_entry_bisect.restype = C.c_double
+        L.orc_entry.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                C.c_double, C.c_double]
+        L.orc_entry.restype = C.c_double
+        L.orc_rates.argtypes = [C.c_int, C.c_double, C.c_double, P(C.c_double), P(C.c_double)]
+        L.orc_coefficients.argtypes = [C.c_int, C.c_double, C.c_int, C.c_void_p]
+        L.orc_run.argtypes = [P(_ODomain), P(_OParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                              C.c_void_p, C.c_void_p]
+        L.orc_gray_run.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_int64, C.c_void_p]
+        L.orc_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def lattice():
+    """(e[19,3], w[19], opp[19]) of the oracle's D3Q19 table."""
+    e = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    o = np.zeros(19, np.int32)
+    lib().orc_lattice(_ptr(e), _ptr(w), _ptr(o))
+    return e, w, o
+
+
+class _Dom:
+    """Keeps the ctypes struct and the sphere array alive together."""
+
+    def __init__(self, dom):
+        self.sph = np.ascontiguousarray(np.asarray(dom.spheres, dtype=np.float64).reshape(-1, 4))
+        s = _ODomain()
+        s.n[:] = [dom.nx, dom.ny, dom.nz]
+        s.periodic[:] = [int(v) for v in dom.periodic]
+        s.wall_lo[:] = [int(v) for v in dom.wall_lo]
+        s.wall_hi[:] = [int(v) for v in dom.wall_hi]
+        s.wall_hi_vel[:] = [float(v) for v in dom.wall_hi_velocity]
+        s.spheres = self.sph.ctypes.data_as(C.POINTER(C.c_double))
+        s.nsph = len(self.sph)
+        s.bc = BC[dom.bc]
+        self.s = s
+        self.shape = (dom.nz, dom.ny, dom.nx)
+
+
+def flags(dom, brute_force=False):
+    """uint8 flags[nz, ny, nx]: 0 fluid, 1 sphere, 2 wall layer."""
+    D = _Dom(dom)
+    f = np.zeros(D.shape, np.uint8)
+    fn = lib().orc_flags_bruteforce if brute_force else lib().orc_flags
+    if fn(C.byref(D.s), _ptr(f)) != 0:
+        raise ValueError("invalid domain")
+    return f
+
+
+def links(dom, fl=None):
+    """Links (x, k) with x fluid and x + e_k not fluid, sorted by (cell, k):
+    returns cell[int64], dir[int8], q[float64], surf[int8]."""
+    D = _Dom(dom)
+    if fl is None:
+        fl = flags(dom)
+    fl = np.ascontiguousarray(fl, dtype=np.uint8)
+    n = lib().orc_count_links(C.byref(D.s), _ptr(fl))
+    if n < 0:
+        raise ValueError("invalid domain")
+    cell = np.zeros(n, np.int64)
+    k = np.zeros(n, np.int8)
+    q = np.zeros(n)
+    surf = np.zeros(n, np.int8)
+    if lib().orc_links(C.byref(D.s), _ptr(fl), n, _ptr(cell), _ptr(k), _ptr(q), _ptr(surf)) != 0:
+        raise ValueError("link construction failed")
+    return cell, k, q, surf
+
+
+def rates(collision, tau_plus, magic_lambda):
+    wp, wm = C.c_double(), C.c_double()
+    rc = lib().orc_rates(1 if collision == "trt" else 0, tau_plus, magic_lambda, C.byref(wp), C.byref(wm))
+    if rc != 0:
+        raise ValueError("relaxation parameters outside the stable range")
+    return wp.value, wm.value
+
+
+def coefficients(bc, q, f2):
+    c = np.zeros(3)
+    lib().orc_coefficients(BC[bc], float(q), int(f2), _ptr(c))
+    return c
+
+
+class Sim:
+    """Two-grid pull simulation on the whole domain or on a window of it.
+
+    window=(org, size) in global (x, y, z) cells; a window smaller than a
+    periodic axis does not wrap, and values read from outside it are NaN.
+    """
+
+    def __init__(self, dom, params, window=None, geometry=None):
+        self.dom = dom
+        self.D = _Dom(dom)
+        p = _OParams()
+        p.trt = 1 if params.collision == "trt" else 0
+        p.tau_plus = params.tau_plus
+        p.magic_lambda = params.magic_lambda
+        p.rho0 = params.rho0
+        p.force[:] = list(params.force)
+        self.p = p
+        self.params = params
+        if geometry is None:
+            fl = flags(dom)
+            geometry = (fl,) + links(dom, fl)
+        fl, cell, k, q, surf = geometry
+        N = (dom.nx, dom.ny, dom.nz)
+        if window is None:
+            org, size = (0, 0, 0), N
+        else:
+            org, size = window
+        self.org = np.array(org, np.int32)
+        self.win = np.array(size, np.int32)
+        wx, wy, wz = size
+        M = wx * wy * wz
+        self.M = M
+        # global coordinates of the window cells (wrapped on periodic axes)
+        gx = (org[0] + np.arange(wx)) % dom.nx
+        gy = (org[1] + np.arange(wy)) % dom.ny
+        gz = (org[2] + np.arange(wz)) % dom.nz
+        if not dom.periodic[2] and (org[2] < 0 or org[2] + wz > dom.nz):
+            raise ValueError("window leaves a non-periodic axis")
+        gid = (gx[None, None, :] + dom.nx * (gy[None, :, None] + dom.ny * gz[:, None, None])).ravel()
+        self.gid = gid
+        self.wflags = np.ascontiguousarray(fl.ravel()[gid])
+        # per window cell link data
+        self.wq = np.full((19, M), np.nan)
+        self.wsurf = np.zeros((19, M), np.int8)
+        pos = np.full(dom.nx * dom.ny * dom.nz, -1, np.int64)
+        pos[gid] = np.arange(M)
+        sel = pos[cell] >= 0
+        wi = pos[cell[sel]]
+        self.wq[k[sel].astype(np.int64), wi] = q[sel]
+        self.wsurf[k[sel].astype(np.int64), wi] = surf[sel]
+        self.ga = np.zeros((19, M))
+        self.gb = np.zeros((19, M))
+        self.rho = np.zeros(M)
+        self.u = np.zeros((3, M))
+        self.steps = 0
+
+    def step(self, n):
+        if n <= 0:
+            return
+        rc = lib().orc_run(C.byref(self.D.s), C.byref(self.p), _ptr(self.org), _ptr(self.win),
+                           _ptr(self.wflags), _ptr(self.wq), _ptr(self.wsurf), _ptr(self.ga),
+                           _ptr(self.gb), int(n), _ptr(self.rho), _ptr(self.u))
+        self.steps += n
+        if rc == -5:
+            raise FloatingPointError("oracle run became unstable")
+        if rc != 0:
+            raise ValueError("invalid parameters")
+
+    def velocity(self):
+        """u[3, wz, wy, wx] of the last step (0 in solid cells)."""
+        wx, wy, wz = self.win
+        return self.u.reshape(3, wz, wy, wx)
+
+    def density(self):
+        wx, wy, wz = self.win
+        return self.rho.reshape(wz, wy, wx)
+
+    def fluid(self):
+        wx, wy, wz = self.win
+        return self.wflags.reshape(wz, wy, wx) == FLUID
+
+
+# ----------------------------------------------------------------------------
+# post-processing (plain FP64 reductions)
+# ----------------------------------------------------------------------------
+
+def plane_profile(u, fluid, axis=2, comp=0):
+    """Planar averages along `axis` (0 x, 1 y, 2 z) of velocity component comp:
+    superficial (sum / plane area), intrinsic (sum / fluid cells of the plane)
+    and porosity (fluid cells / plane area)."""
+    ax = {0: 2, 1: 1, 2: 0}[axis]  # array axis of (z, y, x)
+    other = tuple(a for a in range(3) if a != ax)
+    uc = np.where(fluid, u[comp], 0.0)
+    s = uc.sum(axis=other)
+    nf = fluid.sum(axis=other).astype(np.float64)
+    area = float(np.prod([fluid.shape[a] for a in other]))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        intr = np.where(nf > 0, s / np.maximum(nf, 1), 0.0)
+    return s / area, intr, nf / area
+
+
+def permeability(u_sup_profile, z0, z1, nu, rho0, G):
+    """Darcy's law (eq. (1)) over planes [z0, z1): K = rho0 nu <U_sup> / G."""
+    return rho0 * nu * float(np.mean(u_sup_profile[z0:z1])) / G
+
+
+def totals(rho, u, fluid, rho0=1.0):
+    """Mass sum drho and momentum sum rho0 u over fluid cells."""
+    m = float(np.where(fluid, rho, 0.0).sum())
+    mom = [float(rho0 * np.where(fluid, u[a], 0.0).sum()) for a in range(3)]
+    return m, mom
+
+
+# ----------------------------------------------------------------------------
+# gray column
+# ----------------------------------------------------------------------------
+
+def gray_run(nz, eps, nu_eff, drag, G=(0.0, 0.0, 0.0), walls=True, lid=(0.0, 0.0, 0.0),
+             magic_lambda=3.0 / 16.0, rho0=1.0, nsteps=1000, g=None):
+    """Advance the gray column; returns (u[nz, 3], g[19, nz])."""
+    eps = np.ascontiguousarray(eps, np.float64)
+    nu_eff = np.ascontiguousarray(nu_eff, np.float64)
+    drag = np.ascontiguousarray(drag, np.float64)
+    if g is None:
+        g = np.zeros((19, nz))
+    g = np.ascontiguousarray(g)
+    u = np.zeros((nz, 3))
+    Ga = np.array(G, np.float64)
+    La = np.array(lid, np.float64)
+    rc = lib().orc_gray_run(nz, int(walls), _ptr(eps), _ptr(nu_eff), _ptr(drag), magic_lambda, rho0,
+                            _ptr(Ga), _ptr(La), _ptr(g), int(nsteps), _ptr(u))
+    if rc == -5:
+        raise FloatingPointError("gray column unstable")
+    if rc != 0:
+        raise ValueError("invalid gray parameters")
+    return u, g
+
+
+def gray_to_steady(nz, eps, nu_eff, drag, rel_tol=1e-12, check=1000, max_steps=2_000_000, **kw):
+    g = None
+    prev = None
+    steps = 0
+    while steps < max_steps:
+        u, g = gray_run(nz, eps, nu_eff, drag, nsteps=check, g=g, **kw)
+        steps += check
+        m = float(np.sum(np.abs(u[:, 0])))
+        if prev is not None and abs(m - prev) <= rel_tol * abs(m):
+            return u, steps
+        prev = m
+    return u, steps
