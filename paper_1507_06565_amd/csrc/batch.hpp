@@ -1,0 +1,32 @@
+// Batched pore-scale runs: many independent domains advanced by one
+// persistent kernel (batch.hip).  Internal; reached through the C ABI when a
+// geometry holds more than one domain.
+#pragma once
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lbm {
+
+struct BatchCtx;
+
+lbm_status batch_required_bytes(const std::vector<DomainGeo>& doms, const lbm_params& p, int64_t* bytes);
+lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, double wp, double wm, char* buf,
+                      int64_t bytes, hipStream_t s, BatchCtx** out);
+lbm_status batch_step(BatchCtx* b, int64_t n);
+lbm_status batch_run_to_steady(BatchCtx* b, double rel_tol, int64_t check_every, int64_t max_steps,
+                               int64_t* steps_done);
+lbm_status batch_profile(BatchCtx* b, int dom, int axis, int comp, double* u_sup, double* u_int, double* por);
+lbm_status batch_permeability(BatchCtx* b, int dom, int fa, int z0, int z1, double* k);
+lbm_status batch_fields(BatchCtx* b, int dom, double* rho, double* u);
+lbm_status batch_totals(BatchCtx* b, int dom, double* mass, double* mom);
+lbm_status batch_state_bytes(BatchCtx* b, int64_t* bytes);
+lbm_status batch_save(BatchCtx* b, void* host, int64_t bytes, int64_t steps);
+lbm_status batch_load(BatchCtx* b, const void* host, int64_t bytes);
+lbm_status batch_autotune(BatchCtx* b, int32_t steps_per_trial);
+void batch_destroy(BatchCtx* b);
+
+// error text for the calling thread (defined with the C ABI)
+lbm_status set_error(lbm_status s, const std::string& msg);
+
+}  // namespace lbm

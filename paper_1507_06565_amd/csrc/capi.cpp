@@ -1,0 +1,631 @@
+// C ABI of the pore-scale solver: geometry objects, contexts bound to a
+// caller-owned device buffer and stream, stepping, FP64 reductions,
+// checkpointing and the sweep autotuner.  Single-domain contexts run the
+// fused sweep (two-grid or AA); multi-domain contexts run the batched
+// persistent kernel (batch.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <limits>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "batch.hpp"
+#include "internal.hpp"
+
+using namespace lbm;
+
+struct lbm_geometry {
+    std::vector<DomainGeo> doms;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const std::string& m) {
+    g_err = m;
+    return s;
+}
+
+lbm_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_E_DEVICE;
+}
+
+#define HIP_TRY(expr, what)                         \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Relaxation rates (Sec. 2.1): 1/omega+ = tau+ = 3 nu + 1/2; TRT omega- from
+// Lambda = (tau+ - 1/2)(tau- - 1/2); BGK omega- = omega+.
+lbm_status rates(const lbm_params& p, double& wp, double& wm) {
+    if (p.collision != LBM_BGK && p.collision != LBM_TRT) return fail(LBM_E_INVAL, "unknown collision model");
+    if (!(p.tau_plus > 0.5) || !std::isfinite(p.tau_plus)) return fail(LBM_E_INVAL, "tau_plus must exceed 1/2");
+    if (!(p.rho0 > 0.0)) return fail(LBM_E_INVAL, "rho0 must be positive");
+    for (double f : p.force)
+        if (!std::isfinite(f)) return fail(LBM_E_INVAL, "force must be finite");
+    const double tm = (p.collision == LBM_TRT) ? 0.5 + p.magic_lambda / (p.tau_plus - 0.5) : p.tau_plus;
+    wp = 1.0 / p.tau_plus;
+    wm = 1.0 / tm;
+    if (!(wm > 0.0 && wm < 2.0)) return fail(LBM_E_INVAL, "omega- must lie in (0, 2)");
+    if (p.layout != LBM_LAYOUT_TWOGRID && p.layout != LBM_LAYOUT_AA) return fail(LBM_E_INVAL, "unknown layout");
+    return LBM_OK;
+}
+
+// --------------------------------------------------------- memory plan --
+struct Plan {
+    int64_t N = 0, stride = 0, nb = 0, nl = 0, np = 0, chunk = 0;
+    int64_t off_pop = 0, off_info = 0, off_binfo = 0, off_lparam = 0, off_side = 0, off_red = 0, off_fields = 0;
+    int64_t total = 0;
+};
+
+Plan plan_single(const DomainGeo& g, const lbm_params& p) {
+    Plan P;
+    const auto& d = g.desc;
+    P.N = g.ncells();
+    // pad each population array so that the 19 arrays do not start on the
+    // same power-of-two boundary (HBM channel interleave)
+    P.stride = align_up(P.N, 256) + 320;
+    P.nl = (int64_t)g.lcell.size();
+    int64_t nb = 0;
+    for (size_t i = 0; i < g.lcell.size(); ++i)
+        if (i == 0 || g.lcell[i] != g.lcell[i - 1]) ++nb;
+    P.nb = nb;
+    P.np = std::max(d.nx, std::max(d.ny, d.nz));
+    P.chunk = std::min<int64_t>(P.N, std::max<int64_t>((int64_t)d.nx * d.ny, 1 << 20));
+    int64_t o = 0;
+    const int64_t ngrid = (p.layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
+    P.off_pop = o; o = align_up(o + ngrid * Q * P.stride * 4, 256);
+    P.off_info = o; o = align_up(o + P.N * 4, 256);
+    P.off_binfo = o; o = align_up(o + std::max<int64_t>(P.nb, 1) * 8, 256);
+    P.off_lparam = o; o = align_up(o + std::max<int64_t>(P.nl, 1) * 4, 256);
+    P.off_side = o; o = align_up(o + (p.layout == LBM_LAYOUT_AA ? std::max<int64_t>(P.nl, 1) * 4 : 0), 256);
+    P.off_red = o; o = align_up(o + P.np * 6 * 8, 256);
+    P.off_fields = o; o = align_up(o + P.chunk * 4 * 8, 256);
+    P.total = o;
+    return P;
+}
+
+struct TuneKey {
+    std::string arch;
+    int nx, ny, nz, layout, bc;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, nx, ny, nz, layout, bc) < std::tie(o.arch, o.nx, o.ny, o.nz, o.layout, o.bc);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+
+}  // namespace
+
+lbm_status lbm::set_error(lbm_status s, const std::string& msg) { return fail(s, msg); }
+
+struct lbm_ctx {
+    int ndom = 1;
+    lbm_params p{};
+    double wp = 0, wm = 0;
+    hipStream_t stream = nullptr;
+    char* buf = nullptr;
+    int64_t bytes = 0;
+    int64_t steps = 0;
+    // single domain
+    lbm_domain_desc d{};
+    Plan P;
+    int cur = 0;       // two-grid: which grid holds the state
+    int parity = -1;   // AA: parity of the last step (-1 none)
+    int block = 256;
+    int xcd_remap = 1;
+    SweepArgs sa{};
+    int64_t n_fluid = 0;
+    std::string arch;
+    // batched
+    BatchCtx* batch = nullptr;
+};
+
+namespace {
+
+MomentArgs moment_args(const lbm_ctx* c) {
+    MomentArgs m{};
+    m.A = reinterpret_cast<const float*>(c->buf + c->P.off_pop) + (int64_t)c->cur * Q * c->P.stride;
+    m.stride = c->P.stride;
+    m.info = reinterpret_cast<const int32_t*>(c->buf + c->P.off_info);
+    m.nx = c->d.nx; m.ny = c->d.ny; m.nz = c->d.nz;
+    m.layout = c->p.layout;
+    m.parity = c->parity;
+    m.rho0 = c->p.rho0;
+    for (int a = 0; a < 3; ++a) m.F[a] = c->p.force[a];
+    return m;
+}
+
+lbm_status plane_sums(lbm_ctx* c, int axis, std::vector<double>& out) {
+    const int np = axis == 0 ? c->d.nx : (axis == 1 ? c->d.ny : c->d.nz);
+    double* red = reinterpret_cast<double*>(c->buf + c->P.off_red);
+    HIP_TRY(launch_plane_sums(moment_args(c), axis, red, c->stream), "plane reduction launch");
+    out.assign((size_t)np * 6, 0.0);
+    HIP_TRY(hipMemcpyAsync(out.data(), red, out.size() * 8, hipMemcpyDeviceToHost, c->stream), "copy plane sums");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+    return LBM_OK;
+}
+
+int flow_axis(const lbm_params& p) {
+    int a = 0;
+    for (int i = 1; i < 3; ++i)
+        if (std::fabs(p.force[i]) > std::fabs(p.force[a])) a = i;
+    return a;
+}
+
+lbm_status check_ctx(lbm_ctx* c, int32_t dom) {
+    if (!c) return fail(LBM_E_INVAL, "null context");
+    if (dom < 0 || dom >= c->ndom) return fail(LBM_E_INVAL, "domain index out of range");
+    return LBM_OK;
+}
+
+lbm_status step_single(lbm_ctx* c, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) {
+        SweepArgs a = c->sa;
+        float* base = reinterpret_cast<float*>(c->buf + c->P.off_pop);
+        int par = P_EVEN;
+        if (c->p.layout == LBM_LAYOUT_TWOGRID) {
+            a.A = base + (int64_t)c->cur * Q * c->P.stride;
+            a.B = base + (int64_t)(1 - c->cur) * Q * c->P.stride;
+        } else {
+            a.A = base;
+            a.B = nullptr;
+            par = (c->steps % 2 == 0) ? P_EVEN : P_ODD;
+        }
+        a.xcd_remap = c->xcd_remap;
+        hipError_t e = launch_sweep(a, c->p.layout, par, c->d.bc, c->block, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "sweep launch");
+        if (c->p.layout == LBM_LAYOUT_TWOGRID) c->cur = 1 - c->cur;
+        else c->parity = par;
+        ++c->steps;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_geometry_build(const lbm_domain_desc* domains, int32_t n_domains, lbm_geometry** out) {
+    if (!domains || !out || n_domains < 1) return fail(LBM_E_INVAL, "bad arguments");
+    *out = nullptr;
+    try {
+        auto* g = new lbm_geometry;
+        g->doms.resize(n_domains);
+        for (int i = 0; i < n_domains; ++i) {
+            std::string err;
+            lbm_status s = build_domain(domains[i], g->doms[i], err);
+            if (s != LBM_OK) {
+                delete g;
+                return fail(s, "domain " + std::to_string(i) + ": " + err);
+            }
+        }
+        *out = g;
+        return LBM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_E_NOMEM, "host memory exhausted while building the geometry");
+    }
+}
+
+lbm_status lbm_geometry_flags(const lbm_geometry* g, int32_t dom, uint8_t* host_flags) {
+    if (!g || !host_flags || dom < 0 || dom >= (int)g->doms.size()) return fail(LBM_E_INVAL, "bad arguments");
+    const auto& f = g->doms[dom].flags;
+    std::memcpy(host_flags, f.data(), f.size());
+    return LBM_OK;
+}
+
+lbm_status lbm_geometry_links(const lbm_geometry* g, int32_t dom, int64_t* n, int64_t* cell, int8_t* dir,
+                              double* q) {
+    if (!g || !n || dom < 0 || dom >= (int)g->doms.size()) return fail(LBM_E_INVAL, "bad arguments");
+    const auto& D = g->doms[dom];
+    const int64_t nl = (int64_t)D.lcell.size();
+    if (cell || dir || q) {
+        if (*n < nl) { *n = nl; return fail(LBM_E_NOMEM, "link arrays too small"); }
+        if (cell) std::memcpy(cell, D.lcell.data(), nl * sizeof(int64_t));
+        if (dir) std::memcpy(dir, D.ldir.data(), nl);
+        if (q) std::memcpy(q, D.lq.data(), nl * sizeof(double));
+    }
+    *n = nl;
+    return LBM_OK;
+}
+
+lbm_status lbm_geometry_info(const lbm_geometry* g, int32_t dom, int32_t* n_domains, int64_t* n_fluid,
+                             int64_t* n_links) {
+    if (!g || dom < 0 || dom >= (int)g->doms.size()) return fail(LBM_E_INVAL, "bad arguments");
+    if (n_domains) *n_domains = (int32_t)g->doms.size();
+    if (n_fluid) *n_fluid = g->doms[dom].n_fluid;
+    if (n_links) *n_links = (int64_t)g->doms[dom].lcell.size();
+    return LBM_OK;
+}
+
+void lbm_geometry_free(lbm_geometry* g) { delete g; }
+
+lbm_status lbm_required_bytes(const lbm_geometry* g, const lbm_params* p, int64_t* bytes) {
+    if (!g || !p || !bytes) return fail(LBM_E_INVAL, "bad arguments");
+    double wp, wm;
+    lbm_status s = rates(*p, wp, wm);
+    if (s != LBM_OK) return s;
+    if (g->doms.size() == 1) {
+        *bytes = plan_single(g->doms[0], *p).total;
+        return LBM_OK;
+    }
+    return batch_required_bytes(g->doms, *p, bytes);
+}
+
+lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, int64_t bytes, void* hip_stream,
+                    lbm_ctx** out) {
+    if (!g || !p || !dev_buf || !out) return fail(LBM_E_INVAL, "bad arguments");
+    *out = nullptr;
+    if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0) return fail(LBM_E_INVAL, "device buffer must be 256-byte aligned");
+    double wp, wm;
+    lbm_status s = rates(*p, wp, wm);
+    if (s != LBM_OK) return s;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "no HIP device");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "device properties");
+    auto* c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(LBM_E_NOMEM, "host allocation");
+    c->p = *p;
+    c->wp = wp;
+    c->wm = wm;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->buf = reinterpret_cast<char*>(dev_buf);
+    c->bytes = bytes;
+    c->arch = prop.gcnArchName;
+    c->ndom = (int)g->doms.size();
+    if (c->ndom > 1) {
+        s = batch_init(g->doms, *p, wp, wm, c->buf, bytes, c->stream, &c->batch);
+        if (s != LBM_OK) { delete c; return s; }
+        *out = c;
+        return LBM_OK;
+    }
+    const DomainGeo& G = g->doms[0];
+    c->d = G.desc;
+    c->d.spheres = nullptr;
+    c->d.n_spheres = 0;
+    c->P = plan_single(G, *p);
+    c->n_fluid = G.n_fluid;
+    if (bytes < c->P.total) {
+        delete c;
+        return fail(LBM_E_NOMEM, "device buffer smaller than lbm_required_bytes");
+    }
+    // host images of the cell info, boundary-cell records and link parameters
+    const int64_t N = c->P.N;
+    std::vector<int32_t> info((size_t)N);
+    for (int64_t i = 0; i < N; ++i) info[i] = G.flags[i] == CELL_FLUID ? INFO_FLUID : INFO_SOLID;
+    std::vector<uint32_t> binfo((size_t)std::max<int64_t>(c->P.nb, 1) * 2, 0);
+    std::vector<float> lparam((size_t)std::max<int64_t>(c->P.nl, 1), 0.0f);
+    const bool moving = G.desc.wall_hi_velocity[0] != 0.0 || G.desc.wall_hi_velocity[1] != 0.0 ||
+                        G.desc.wall_hi_velocity[2] != 0.0;
+    const int nx = G.desc.nx, ny = G.desc.ny, nz = G.desc.nz;
+    int64_t b = -1;
+    for (int64_t i = 0; i < c->P.nl; ++i) {
+        const int64_t cell = G.lcell[i];
+        const int k = G.ldir[i];
+        if (i == 0 || cell != G.lcell[i - 1]) {
+            ++b;
+            info[cell] = (int32_t)b;
+            binfo[2 * b + 0] = 0;
+            binfo[2 * b + 1] = (uint32_t)i;
+        }
+        binfo[2 * b] |= 1u << (k - 1);
+        // second fluid node x - e_k decides the interpolation fallback
+        const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((int64_t)nx * ny));
+        int x2 = x - D3Q19::ex[k], y2 = y - D3Q19::ey[k], z2 = z - D3Q19::ez[k];
+        x2 = (x2 + nx) % nx; y2 = (y2 + ny) % ny; z2 = (z2 + nz) % nz;
+        const bool f2 = G.flags[x2 + (int64_t)nx * (y2 + (int64_t)ny * z2)] == CELL_FLUID;
+        const double q = G.lq[i];
+        float prm = 0.0f;
+        if (moving && G.lsurf[i] == SURF_WALL_HI) {
+            prm = std::numeric_limits<float>::quiet_NaN();
+        } else if (G.desc.bc == LBM_BC_CLI) {
+            prm = f2 ? (float)((1.0 - 2.0 * q) / (1.0 + 2.0 * q)) : 0.0f;
+        } else if (G.desc.bc == LBM_BC_BOUZIDI) {
+            prm = (q < 0.5 && !f2) ? 0.5f : (float)q;
+        }
+        lparam[i] = prm;
+    }
+    SweepArgs& a = c->sa;
+    a.stride = c->P.stride;
+    a.info = reinterpret_cast<const int32_t*>(c->buf + c->P.off_info);
+    a.binfo = reinterpret_cast<const uint2*>(c->buf + c->P.off_binfo);
+    a.lparam = reinterpret_cast<const float*>(c->buf + c->P.off_lparam);
+    a.side = reinterpret_cast<float*>(c->buf + c->P.off_side);
+    a.nx = nx; a.ny = ny; a.nz = nz; a.ncells = (int32_t)N;
+    a.wp = (float)wp; a.wm = (float)wm;
+    a.cp = (float)(1.0 - 0.5 * wp); a.cm = (float)(1.0 - 0.5 * wm);
+    a.rho0 = (float)p->rho0; a.inv_rho0 = (float)(1.0 / p->rho0);
+    for (int i = 0; i < 3; ++i) a.F[i] = (float)p->force[i];
+    for (int k = 0; k < Q; ++k) {
+        const double eu = D3Q19::ex[k] * G.desc.wall_hi_velocity[0] + D3Q19::ey[k] * G.desc.wall_hi_velocity[1] +
+                          D3Q19::ez[k] * G.desc.wall_hi_velocity[2];
+        a.wterm[k] = (float)(6.0 * weight(k) * p->rho0 * eu);
+    }
+    // launch configuration from the tuning cache, if any
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find({c->arch, nx, ny, nz, p->layout, G.desc.bc});
+        if (it != g_tune_cache.end()) { c->block = it->second.first; c->xcd_remap = it->second.second; }
+    }
+    hipError_t e;
+    const int64_t ngrid = (p->layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
+    e = launch_fill_zero(reinterpret_cast<float*>(c->buf + c->P.off_pop), ngrid * Q * c->P.stride, c->stream);
+    if (e == hipSuccess && p->layout == LBM_LAYOUT_AA)
+        e = launch_fill_zero(a.side, std::max<int64_t>(c->P.nl, 1), c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->buf + c->P.off_info, info.data(), N * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->buf + c->P.off_binfo, binfo.data(), binfo.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->buf + c->P.off_lparam, lparam.data(), lparam.size() * 4, hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host images go out of scope
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "context upload");
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return fail(LBM_E_INVAL, "bad arguments");
+    if (c->batch) {
+        lbm_status s = batch_step(c->batch, n);
+        if (s == LBM_OK) c->steps += n;
+        return s;
+    }
+    return step_single(c, n);
+}
+
+lbm_status lbm_run_to_steady(lbm_ctx* c, double rel_tol, int64_t check_every, int64_t max_steps,
+                             int64_t* steps_done) {
+    if (!c || !(rel_tol >= 0) || check_every < 1 || max_steps < 0 || !steps_done)
+        return fail(LBM_E_INVAL, "bad arguments");
+    if (c->batch) return batch_run_to_steady(c->batch, rel_tol, check_every, max_steps, steps_done);
+    const int fa = flow_axis(c->p);
+    double prev = NAN;
+    int64_t done = 0;
+    std::vector<double> ps;
+    while (done < max_steps) {
+        const int64_t n = std::min(check_every, max_steps - done);
+        lbm_status s = step_single(c, n);
+        if (s != LBM_OK) return s;
+        done += n;
+        s = plane_sums(c, 2, ps);
+        if (s != LBM_OK) return s;
+        double U = 0.0, bad = 0.0;
+        for (int z = 0; z < c->d.nz; ++z) { U += ps[z * 6 + 1 + fa]; bad += ps[z * 6 + 5]; }
+        if (bad > 0) { *steps_done = done; return fail(LBM_E_UNSTABLE, "NaN or |u| >= 0.4 in the flow field"); }
+        if (n == check_every && std::isfinite(prev) && std::fabs(U - prev) <= rel_tol * std::fabs(U)) {
+            *steps_done = done;
+            return LBM_OK;
+        }
+        prev = U;
+    }
+    *steps_done = max_steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_average_profile(lbm_ctx* c, int32_t dom, int32_t axis, int32_t comp, double* u_sup, double* u_int,
+                               double* porosity) {
+    lbm_status s = check_ctx(c, dom);
+    if (s != LBM_OK) return s;
+    if (axis < 0 || axis > 2 || comp < 0 || comp > 2) return fail(LBM_E_INVAL, "axis and comp must be 0, 1 or 2");
+    if (c->batch) return batch_profile(c->batch, dom, axis, comp, u_sup, u_int, porosity);
+    std::vector<double> ps;
+    s = plane_sums(c, axis, ps);
+    if (s != LBM_OK) return s;
+    const int np = axis == 0 ? c->d.nx : (axis == 1 ? c->d.ny : c->d.nz);
+    const double area = (double)c->P.N / np;
+    for (int i = 0; i < np; ++i) {
+        const double sum = ps[i * 6 + 1 + comp], nf = ps[i * 6 + 4];
+        if (u_sup) u_sup[i] = sum / area;
+        if (u_int) u_int[i] = nf > 0 ? sum / nf : 0.0;
+        if (porosity) porosity[i] = nf / area;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_permeability(lbm_ctx* c, int32_t dom, int32_t fa, int32_t z0, int32_t z1, double* k) {
+    lbm_status s = check_ctx(c, dom);
+    if (s != LBM_OK) return s;
+    if (!k || fa < 0 || fa > 2) return fail(LBM_E_INVAL, "bad arguments");
+    if (c->batch) return batch_permeability(c->batch, dom, fa, z0, z1, k);
+    if (z0 < 0 || z1 > c->d.nz || z0 >= z1) return fail(LBM_E_INVAL, "bad plane range");
+    if (c->p.force[fa] == 0.0) return fail(LBM_E_INVAL, "no body force along the flow axis");
+    std::vector<double> sup((size_t)c->d.nz);
+    s = lbm_average_profile(c, dom, 2, fa, sup.data(), nullptr, nullptr);
+    if (s != LBM_OK) return s;
+    double m = 0;
+    for (int z = z0; z < z1; ++z) m += sup[z];
+    m /= (z1 - z0);
+    const double nu = (c->p.tau_plus - 0.5) / 3.0;
+    *k = c->p.rho0 * nu * m / c->p.force[fa];
+    return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_ctx* c, int32_t dom, double* host_rho, double* host_u) {
+    lbm_status s = check_ctx(c, dom);
+    if (s != LBM_OK) return s;
+    if (c->batch) return batch_fields(c->batch, dom, host_rho, host_u);
+    const int64_t N = c->P.N, chunk = c->P.chunk;
+    double* dv = reinterpret_cast<double*>(c->buf + c->P.off_fields);
+    std::vector<double> h((size_t)chunk * 4);
+    for (int64_t c0 = 0; c0 < N; c0 += chunk) {
+        const int64_t n = std::min(chunk, N - c0);
+        HIP_TRY(launch_fields(moment_args(c), c0, n, dv, c->stream), "fields launch");
+        HIP_TRY(hipMemcpyAsync(h.data(), dv, n * 4 * 8, hipMemcpyDeviceToHost, c->stream), "copy fields");
+        HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+        if (host_rho) std::memcpy(host_rho + c0, h.data(), n * 8);
+        if (host_u)
+            for (int a = 0; a < 3; ++a) std::memcpy(host_u + a * N + c0, h.data() + (a + 1) * n, n * 8);
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_totals(lbm_ctx* c, int32_t dom, double* mass, double momentum[3]) {
+    lbm_status s = check_ctx(c, dom);
+    if (s != LBM_OK) return s;
+    if (c->batch) return batch_totals(c->batch, dom, mass, momentum);
+    std::vector<double> ps;
+    s = plane_sums(c, 2, ps);
+    if (s != LBM_OK) return s;
+    double m = 0, j[3] = {0, 0, 0}, bad = 0;
+    for (int z = 0; z < c->d.nz; ++z) {
+        m += ps[z * 6];
+        for (int a = 0; a < 3; ++a) j[a] += ps[z * 6 + 1 + a];
+        bad += ps[z * 6 + 5];
+    }
+    if (mass) *mass = m;
+    if (momentum)
+        for (int a = 0; a < 3; ++a) momentum[a] = c->p.rho0 * j[a];
+    if (bad > 0) return fail(LBM_E_UNSTABLE, "NaN or |u| >= 0.4 in the flow field");
+    return LBM_OK;
+}
+
+// checkpoint image: 4 int64 header {magic, steps, parity, cur} + populations
+// of the current grid + side buffer
+static const int64_t kMagic = 0x4c424d53544154;  // "LBMSTAT"
+
+lbm_status lbm_state_bytes(lbm_ctx* c, int64_t* bytes) {
+    if (!c || !bytes) return fail(LBM_E_INVAL, "bad arguments");
+    if (c->batch) return batch_state_bytes(c->batch, bytes);
+    *bytes = 32 + Q * c->P.stride * 4 + (c->p.layout == LBM_LAYOUT_AA ? c->P.nl * 4 : 0);
+    return LBM_OK;
+}
+
+lbm_status lbm_save(lbm_ctx* c, void* host_buf, int64_t bytes) {
+    int64_t need = 0;
+    lbm_status s = lbm_state_bytes(c, &need);
+    if (s != LBM_OK) return s;
+    if (!host_buf || bytes < need) return fail(LBM_E_NOMEM, "host buffer too small");
+    if (c->batch) return batch_save(c->batch, host_buf, bytes, c->steps);
+    int64_t* h = reinterpret_cast<int64_t*>(host_buf);
+    h[0] = kMagic; h[1] = c->steps; h[2] = c->parity; h[3] = 0;
+    char* dst = reinterpret_cast<char*>(host_buf) + 32;
+    const char* pop = c->buf + c->P.off_pop + (int64_t)c->cur * Q * c->P.stride * 4;
+    HIP_TRY(hipMemcpyAsync(dst, pop, Q * c->P.stride * 4, hipMemcpyDeviceToHost, c->stream), "save populations");
+    if (c->p.layout == LBM_LAYOUT_AA && c->P.nl > 0)
+        HIP_TRY(hipMemcpyAsync(dst + Q * c->P.stride * 4, c->buf + c->P.off_side, c->P.nl * 4, hipMemcpyDeviceToHost,
+                               c->stream), "save side buffer");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+    return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx* c, const void* host_buf, int64_t bytes) {
+    int64_t need = 0;
+    lbm_status s = lbm_state_bytes(c, &need);
+    if (s != LBM_OK) return s;
+    if (!host_buf || bytes < need) return fail(LBM_E_INVAL, "state image too small");
+    const int64_t* h = reinterpret_cast<const int64_t*>(host_buf);
+    if (h[0] != kMagic) return fail(LBM_E_INVAL, "not a state image");
+    if (c->batch) {
+        s = batch_load(c->batch, host_buf, bytes);
+        if (s == LBM_OK) c->steps = h[1];
+        return s;
+    }
+    const char* src = reinterpret_cast<const char*>(host_buf) + 32;
+    c->cur = 0;
+    HIP_TRY(hipMemcpyAsync(c->buf + c->P.off_pop, src, Q * c->P.stride * 4, hipMemcpyHostToDevice, c->stream),
+            "load populations");
+    if (c->p.layout == LBM_LAYOUT_AA && c->P.nl > 0)
+        HIP_TRY(hipMemcpyAsync(c->buf + c->P.off_side, src + Q * c->P.stride * 4, c->P.nl * 4, hipMemcpyHostToDevice,
+                               c->stream), "load side buffer");
+    HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+    c->steps = h[1];
+    c->parity = (int)h[2];
+    return LBM_OK;
+}
+
+lbm_status lbm_steps_done(lbm_ctx* c, int64_t* steps) {
+    if (!c || !steps) return fail(LBM_E_INVAL, "bad arguments");
+    *steps = c->steps;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t xcd_remap) {
+    if (!c || c->batch) return fail(LBM_E_INVAL, "launch shape applies to single-domain contexts");
+    if (block != 128 && block != 256 && block != 512 && block != 1024) return fail(LBM_E_INVAL, "block must be 128, 256, 512 or 1024");
+    c->block = block;
+    c->xcd_remap = xcd_remap ? 1 : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_launch(lbm_ctx* c, int32_t* block, int32_t* xcd_remap) {
+    if (!c || c->batch) return fail(LBM_E_INVAL, "launch shape applies to single-domain contexts");
+    if (block) *block = c->block;
+    if (xcd_remap) *xcd_remap = c->xcd_remap;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial) {
+    if (!c || steps_per_trial < 2) return fail(LBM_E_INVAL, "bad arguments");
+    if (c->batch) return batch_autotune(c->batch, steps_per_trial);
+    int64_t sb = 0;
+    lbm_status s = lbm_state_bytes(c, &sb);
+    if (s != LBM_OK) return s;
+    std::vector<char> saved;
+    try {
+        saved.resize((size_t)sb);
+    } catch (const std::bad_alloc&) {
+        return fail(LBM_E_NOMEM, "host memory for the autotuner's state copy");
+    }
+    s = lbm_save(c, saved.data(), sb);
+    if (s != LBM_OK) return s;
+    const int blocks[] = {128, 256, 512, 1024};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    float best = 1e30f;
+    int bb = c->block, br = c->xcd_remap;
+    for (int blk : blocks)
+        for (int remap = 0; remap < 2; ++remap) {
+            c->block = blk;
+            c->xcd_remap = remap;
+            s = step_single(c, 2);  // warm-up (even + odd for AA)
+            if (s != LBM_OK) break;
+            hipEventRecord(e0, c->stream);
+            s = step_single(c, steps_per_trial);
+            if (s != LBM_OK) break;
+            hipEventRecord(e1, c->stream);
+            hipEventSynchronize(e1);
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; bb = blk; br = remap; }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->block = bb;
+    c->xcd_remap = br;
+    lbm_status s2 = lbm_load(c, saved.data(), sb);
+    if (s != LBM_OK) return s;
+    if (s2 != LBM_OK) return s2;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[{c->arch, c->d.nx, c->d.ny, c->d.nz, c->p.layout, c->d.bc}] = {bb, br};
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    if (c->batch) batch_destroy(c->batch);
+    delete c;
+}
+
+}  // extern "C"

@@ -74,7 +74,7 @@ def _pairs(tree, rmax2):
 
 def pack_spheres(seed: int, box: tuple, periodic: tuple, r_range: tuple,
                  solid_volume: float, zc_bounds=None, gap: float = 2.0 ** -9,
-                 max_iter: int = 4000, shrink: float = 0.995):
+                 max_iter: int = 3000, shrink: float = 0.995, relax_tol: float = 0.02):
     """Random non-overlapping polydisperse spheres.
 
     box: (Lx, Ly, Lz) extent of the placement region; centres x,y in [0, L),
@@ -124,35 +124,45 @@ def pack_spheres(seed: int, box: tuple, periodic: tuple, r_range: tuple,
         return d
 
     P = clamp(P)
-    it = 0
-    while True:
+
+    def overlaps(P, R):
         rmax = 2.0 * R.max() + gap
         tree = cKDTree(np.where(per, np.mod(P, L), P + 1e4), boxsize=boxsize)
         pr = _pairs(tree, rmax)
-        if len(pr):
-            i, j = pr[:, 0], pr[:, 1]
-            d = min_image(P[j] - P[i])
-            dist = np.sqrt((d * d).sum(1))
-            want = R[i] + R[j] + gap
-            ov = want - dist
-            m = ov > 0
-            i, j, d, dist, ov = i[m], j[m], d[m], dist[m], ov[m]
-        else:
-            ov = np.zeros(0)
-        if len(ov) == 0:
+        if len(pr) == 0:
+            return (np.zeros(0, int),) * 2 + (np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+        i, j = pr[:, 0], pr[:, 1]
+        d = min_image(P[j] - P[i])
+        dist = np.sqrt((d * d).sum(1))
+        ov = R[i] + R[j] + gap - dist
+        m = ov > 0
+        return i[m], j[m], d[m], dist[m], ov[m]
+
+    # collective rearrangement: push overlapping pairs apart (Jacobi sweeps)
+    # until the largest overlap is below relax_tol ...
+    for it in range(max_iter):
+        i, j, d, dist, ov = overlaps(P, R)
+        if len(ov) == 0 or ov.max() <= relax_tol:
             break
-        it += 1
-        if it % max_iter == 0:
-            R *= shrink  # jammed: shrink all radii slightly and continue
         dist = np.maximum(dist, 1e-12)
         u = d / dist[:, None]
-        # heavier (larger) spheres move less
-        wi = R[j] ** 3 / (R[i] ** 3 + R[j] ** 3)
+        wi = R[j] ** 3 / (R[i] ** 3 + R[j] ** 3)  # heavier spheres move less
         wj = 1.0 - wi
         disp = np.zeros_like(P)
         np.add.at(disp, i, -(ov * wi * 0.55)[:, None] * u)
         np.add.at(disp, j, (ov * wj * 0.55)[:, None] * u)
         P = clamp(P + disp)
+        if (it + 1) % 500 == 0:
+            R *= shrink  # jammed: shrink all radii slightly and continue
+    # ... then remove what is left by shrinking the spheres involved
+    for _ in range(200):
+        i, j, d, dist, ov = overlaps(P, R)
+        if len(ov) == 0:
+            break
+        cut = np.zeros(n)
+        np.maximum.at(cut, i, 0.5 * ov + gap)
+        np.maximum.at(cut, j, 0.5 * ov + gap)
+        R = R - cut
 
     S = np.empty((n, 4))
     S[:, :3] = P
