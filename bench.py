@@ -1,0 +1,225 @@
+"""Benchmark of the pore-scale hot path on one MI355X.
+
+Workload (default): the large coupled free-channel / porous-bed domain,
+512 x 256 x 1024 cells, sphere bed (radii U[8,16], porosity 0.45) in the lower
+half, TRT with Lambda = 3/16, tau+ = 0.7, body force 5e-7, CLI bounce-back at
+the spheres, FP32 shifted populations in the AA in-place layout.  One step is
+one full time step of the hot path: the fused stream + collide sweep with
+the interpolated bounce-back of every boundary link.  Inputs are resident in
+HBM before the timed region starts.
+
+Prints ONE JSON line (rank 0) with MLUPS as `value`, plus the roofline of the
+sweep kernel and the CPU oracle's rate on a bounded sample of the workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-check]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_fluid, n_cells, n_links):
+    """Minimal HBM bytes of one sweep step: 19 FP32 loads + 19 FP32 stores per
+    fluid cell, the 4 B cell word of every cell and, per boundary link, its
+    4 B coefficient read and the 4 B partial bounce-back value stored."""
+    return 152 * n_fluid + 4 * n_cells + 8 * n_links
+
+
+def sampled_window_check(dom, params, ctx_factory, geo, nsteps=8, nwin=12, seed=0):
+    """FP32 GPU vs FP64 oracle on sampled cells of the full-size domain: each
+    sampled cell's neighbourhood is run on the oracle in a window whose edge is
+    more than nsteps cells away (one cell of light cone per step)."""
+    import numpy as np
+
+    import oracle
+
+    ctx = ctx_factory()
+    ctx.step(nsteps)
+    _, u = ctx.fields()
+    rng = np.random.default_rng(seed)
+    h = nsteps + 2
+    w = 2 * h + 4
+    num = den = 0.0
+    for _ in range(nwin):
+        cz = int(rng.integers(h + 1, dom.nz - h - 5))
+        org = (int(rng.integers(0, dom.nx)), int(rng.integers(0, dom.ny)), cz - h)
+        sim = oracle.Sim(dom, params, window=(org, (w, w, w)), geometry=geo)
+        sim.step(nsteps)
+        uw = sim.velocity()
+        fw = sim.fluid()
+        for zz in range(h, w - h):
+            for yy in range(h, w - h):
+                for xx in range(h, w - h):
+                    if not fw[zz, yy, xx]:
+                        continue
+                    gx, gy, gz = (org[0] + xx) % dom.nx, (org[1] + yy) % dom.ny, org[2] + zz
+                    ref = uw[:, zz, yy, xx]
+                    got = u[:, gz, gy, gx]
+                    num += float(((got - ref) ** 2).sum())
+                    den += float((ref ** 2).sum())
+    del ctx
+    return (num / den) ** 0.5 if den > 0 else float("nan")
+
+
+def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0):
+    """The FP64 oracle, as it is, on a slab of the workload straddling the
+    bed surface; one step calibrates the step count to about budget_s."""
+    import oracle
+
+    sim = oracle.Sim(dom, params, window=((0, 0, z0), (dom.nx, dom.ny, nz_win)), geometry=geo_oracle)
+    t = time.perf_counter()
+    sim.step(1)
+    t1 = time.perf_counter() - t
+    nsteps = int(max(1, min(50, budget_s / max(t1, 1e-3))))
+    t = time.perf_counter()
+    sim.step(nsteps)
+    dt = time.perf_counter() - t
+    cells = dom.nx * dom.ny * nz_win
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{dom.nx}x{dom.ny}x{nz_win} slab (z {z0}..{z0 + nz_win - 1}) of the workload, "
+                      f"{nsteps} steps, FP64 two-grid, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 2 GiB device copy (reference for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the z-slab decomposition is described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1507_06565_amd import lbm, workloads as W
+
+    t0 = time.perf_counter()
+    dom, params, eps = W.large_c2()
+    log(f"workload: {dom.nx}x{dom.ny}x{dom.nz}, {len(dom.spheres)} spheres, bed porosity {eps:.4f} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    geo = lbm.Geometry(dom)
+    _, n_fluid, n_links = geo.info()
+    log(f"geometry: {n_fluid} fluid cells, {n_links} links "
+        f"({time.perf_counter() - t0:.1f} s)")
+    n_cells = dom.nx * dom.ny * dom.nz
+
+    torch.cuda.set_device(0)
+    check = None
+    geo_oracle = None
+    if not args.no_check or not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        fl = oracle.flags(dom)
+        geo_oracle = (fl,) + oracle.links(dom, fl)
+        log(f"oracle geometry ({time.perf_counter() - t0:.1f} s)")
+    if not args.no_check:
+        t0 = time.perf_counter()
+        check = sampled_window_check(dom, params, lambda: lbm.Context(geo, params), geo_oracle, nsteps=8, nwin=12)
+        torch.cuda.empty_cache()
+        log(f"sampled-window FP32 vs FP64 rel L2 after 8 steps: {check:.3e} ({time.perf_counter() - t0:.1f} s)")
+
+    if args.copy_probe:
+        a = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x copy of 2 GiB (2 GiB read + 2 GiB written per launch)")
+        del a, b
+        torch.cuda.empty_cache()
+
+    ctx = lbm.Context(geo, params)
+    if not args.no_autotune:
+        log("autotuned launch (block, flags):", ctx.autotune(10))
+    block, flags = ctx.get_launch()
+    stream = ctx.stream
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    mass, mom = ctx.totals()
+    log(f"timed {args.steps} steps: {ms:.1f} ms; mass sum {mass:.3e}; momentum x {mom[0]:.4e}")
+
+    alg = algorithmic_bytes(n_fluid, n_cells, n_links)
+    achieved = alg / (ms_per_step * 1e-3) / 1e9
+    mlups = n_cells / (ms_per_step * 1e-3) / 1e6
+    mflups = n_fluid / (ms_per_step * 1e-3) / 1e6
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "sweep_aa_512x256x1024_traffic.json")
+    if os.path.exists(tf):
+        with open(tf) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_hash") == _sweep_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(dom, params, geo_oracle, 480, 64)
+        log("cpu baseline:", cpu)
+
+    out = {
+        "metric": "MLUPS + HBM GB/s (% peak) at stated FP32 error; closure vs pore-scale speed/err",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "coupled channel over sphere bed 512x256x1024, radii U[8,16], "
+                               "bed porosity 0.45, TRT Lambda 3/16 tau 0.7, force 5e-7, CLI, AA, FP32 shifted",
+                   "nx": dom.nx, "ny": dom.ny, "nz": dom.nz, "cells": n_cells, "fluid_cells": n_fluid,
+                   "links": n_links, "layout": "aa", "block": block, "launch_flags": flags},
+        "mflups": round(mflups, 1),
+        "effective_gbs": round(achieved, 1),
+        "fp32_rel_l2_vs_fp64_oracle": check,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _sweep_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sweep.hip", "internal.hpp", "lattice.hpp"):
+        with open(os.path.join(ROOT, "paper_1507_06565_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -209,13 +209,18 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* host_buf, int64_t bytes);
 lbm_status lbm_steps_done(lbm_ctx* ctx, int64_t* steps);
 
 /* Sweep launch configuration of a single-domain context: cells per workgroup
- * (64, 128, 256, 512 or 1024) and whether consecutive workgroups are mapped to
- * one XCD (1) or round-robin (0).  Every configuration gives bit-identical
- * results.  lbm_autotune times the candidates on the context's own state
- * (then restores it) and keeps the fastest; the choice is cached per process
- * by (architecture, shape, layout).  Synchronises. */
-lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t xcd_remap);
-lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* block, int32_t* xcd_remap);
+ * (64, 128, 256, 512 or 1024) and flags: LBM_LAUNCH_XCD_REMAP deals
+ * consecutive tiles to one XCD instead of round-robin, LBM_LAUNCH_NONTEMPORAL
+ * marks the aligned population streams non-temporal.  Every configuration
+ * gives bit-identical results.  lbm_autotune times every configuration for
+ * steps_per_trial steps on the context itself, keeps the fastest and restores
+ * the state (host copy, or the rest state if no step was taken); the choice
+ * is cached per process by (architecture, shape, layout, bc) and reused by
+ * later lbm_init calls.  Synchronises. */
+#define LBM_LAUNCH_XCD_REMAP 1
+#define LBM_LAUNCH_NONTEMPORAL 2
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t flags);
+lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* block, int32_t* flags);
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps_per_trial);
 
 /* Destroy a context (the device buffer stays the caller's). */

@@ -66,8 +66,8 @@ lbm_status rates(const lbm_params& p, double& wp, double& wm) {
 
 // --------------------------------------------------------- memory plan --
 struct Plan {
-    int64_t N = 0, stride = 0, nb = 0, nl = 0, np = 0, chunk = 0;
-    int64_t off_pop = 0, off_info = 0, off_binfo = 0, off_lparam = 0, off_side = 0, off_red = 0, off_fields = 0;
+    int64_t N = 0, stride = 0, nb = 0, nl = 0, np = 0, chunk = 0, nseed = 0;
+    int64_t off_pop = 0, off_info = 0, off_segbase = 0, off_lparam = 0, off_seed = 0, off_red = 0, off_fields = 0;
     int64_t total = 0;
 };
 
@@ -83,15 +83,19 @@ Plan plan_single(const DomainGeo& g, const lbm_params& p) {
     for (size_t i = 0; i < g.lcell.size(); ++i)
         if (i == 0 || g.lcell[i] != g.lcell[i - 1]) ++nb;
     P.nb = nb;
+    const bool moving = d.wall_hi_velocity[0] != 0.0 || d.wall_hi_velocity[1] != 0.0 || d.wall_hi_velocity[2] != 0.0;
+    if (moving)
+        for (size_t i = 0; i < g.lsurf.size(); ++i)
+            if (g.lsurf[i] == SURF_WALL_HI) ++P.nseed;
     P.np = std::max(d.nx, std::max(d.ny, d.nz));
     P.chunk = std::min<int64_t>(P.N, std::max<int64_t>((int64_t)d.nx * d.ny, 1 << 20));
     int64_t o = 0;
     const int64_t ngrid = (p.layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
     P.off_pop = o; o = align_up(o + ngrid * Q * P.stride * 4, 256);
     P.off_info = o; o = align_up(o + P.N * 4, 256);
-    P.off_binfo = o; o = align_up(o + std::max<int64_t>(P.nb, 1) * 8, 256);
-    P.off_lparam = o; o = align_up(o + std::max<int64_t>(P.nl, 1) * 4, 256);
-    P.off_side = o; o = align_up(o + (p.layout == LBM_LAYOUT_AA ? std::max<int64_t>(P.nl, 1) * 4 : 0), 256);
+    P.off_segbase = o; o = align_up(o + ((P.N >> SEG_SHIFT) + 1) * 4, 256);
+    P.off_lparam = o; o = align_up(o + (P.nl + Q) * 4, 256);
+    P.off_seed = o; o = align_up(o + std::max<int64_t>(P.nseed, 1) * 12, 256);
     P.off_red = o; o = align_up(o + P.np * 6 * 8, 256);
     P.off_fields = o; o = align_up(o + P.chunk * 4 * 8, 256);
     P.total = o;
@@ -127,6 +131,7 @@ struct lbm_ctx {
     int parity = -1;   // AA: parity of the last step (-1 none)
     int block = 256;
     int xcd_remap = 1;
+    int nt = 0;
     SweepArgs sa{};
     int64_t n_fluid = 0;
     std::string arch;
@@ -140,7 +145,7 @@ MomentArgs moment_args(const lbm_ctx* c) {
     MomentArgs m{};
     m.A = reinterpret_cast<const float*>(c->buf + c->P.off_pop) + (int64_t)c->cur * Q * c->P.stride;
     m.stride = c->P.stride;
-    m.info = reinterpret_cast<const int32_t*>(c->buf + c->P.off_info);
+    m.info = reinterpret_cast<const uint32_t*>(c->buf + c->P.off_info);
     m.nx = c->d.nx; m.ny = c->d.ny; m.nz = c->d.nz;
     m.layout = c->p.layout;
     m.parity = c->parity;
@@ -185,7 +190,12 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
             a.B = nullptr;
             par = (c->steps % 2 == 0) ? P_EVEN : P_ODD;
         }
+        for (int k = 0; k < Q; ++k) {
+            a.pa[k] = a.A + k * c->P.stride;
+            a.pb[k] = a.B ? a.B + k * c->P.stride : nullptr;
+        }
         a.xcd_remap = c->xcd_remap;
+        a.nt = c->nt;
         hipError_t e = launch_sweep(a, c->p.layout, par, c->d.bc, c->block, c->stream);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
         if (c->p.layout == LBM_LAYOUT_TWOGRID) c->cur = 1 - c->cur;
@@ -193,6 +203,22 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
         ++c->steps;
     }
     return LBM_OK;
+}
+
+// rest state: every population zero (f = w rho0), moving-wall partial values
+// seeded
+hipError_t reset_state(lbm_ctx* c) {
+    const int64_t ngrid = (c->p.layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
+    float* pop = reinterpret_cast<float*>(c->buf + c->P.off_pop);
+    hipError_t e = launch_fill_zero(pop, ngrid * Q * c->P.stride, c->stream);
+    if (e == hipSuccess && c->P.nseed > 0)
+        e = launch_scatter(pop, reinterpret_cast<const int64_t*>(c->buf + c->P.off_seed),
+                           reinterpret_cast<const float*>(c->buf + c->P.off_seed + c->P.nseed * 8), c->P.nseed,
+                           c->stream);
+    c->steps = 0;
+    c->cur = 0;
+    c->parity = -1;
+    return e;
 }
 
 }  // namespace
@@ -307,24 +333,34 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
     }
     // host images of the cell info, boundary-cell records and link parameters
     const int64_t N = c->P.N;
-    std::vector<int32_t> info((size_t)N);
-    for (int64_t i = 0; i < N; ++i) info[i] = G.flags[i] == CELL_FLUID ? INFO_FLUID : INFO_SOLID;
-    std::vector<uint32_t> binfo((size_t)std::max<int64_t>(c->P.nb, 1) * 2, 0);
-    std::vector<float> lparam((size_t)std::max<int64_t>(c->P.nl, 1), 0.0f);
+    std::vector<uint32_t> info((size_t)N);
+    for (int64_t i = 0; i < N; ++i) info[i] = G.flags[i] == CELL_FLUID ? 0u : CELL_SOLID_WORD;
+    const int64_t nseg = (N >> SEG_SHIFT) + 1;
+    std::vector<int32_t> segbase((size_t)nseg, 0);
+    std::vector<float> lparam((size_t)(c->P.nl + Q), 0.0f);
     const bool moving = G.desc.wall_hi_velocity[0] != 0.0 || G.desc.wall_hi_velocity[1] != 0.0 ||
                         G.desc.wall_hi_velocity[2] != 0.0;
     const int nx = G.desc.nx, ny = G.desc.ny, nz = G.desc.nz;
-    int64_t b = -1;
+    {
+        // first link of every segment (links are sorted by cell)
+        int64_t li = 0;
+        for (int64_t sg = 0; sg < nseg; ++sg) {
+            while (li < c->P.nl && (G.lcell[li] >> SEG_SHIFT) < sg) ++li;
+            segbase[sg] = (int32_t)li;
+        }
+    }
     for (int64_t i = 0; i < c->P.nl; ++i) {
         const int64_t cell = G.lcell[i];
         const int k = G.ldir[i];
         if (i == 0 || cell != G.lcell[i - 1]) {
-            ++b;
-            info[cell] = (int32_t)b;
-            binfo[2 * b + 0] = 0;
-            binfo[2 * b + 1] = (uint32_t)i;
+            const int64_t off = i - segbase[cell >> SEG_SHIFT];
+            if (off < 0 || off >= (1 << 14)) {
+                delete c;
+                return fail(LBM_E_INVAL, "internal: link offset outside its segment");
+            }
+            info[cell] = (uint32_t)off << 18;
         }
-        binfo[2 * b] |= 1u << (k - 1);
+        info[cell] |= 1u << (k - 1);
         // second fluid node x - e_k decides the interpolation fallback
         const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((int64_t)nx * ny));
         int x2 = x - D3Q19::ex[k], y2 = y - D3Q19::ey[k], z2 = z - D3Q19::ez[k];
@@ -343,10 +379,9 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
     }
     SweepArgs& a = c->sa;
     a.stride = c->P.stride;
-    a.info = reinterpret_cast<const int32_t*>(c->buf + c->P.off_info);
-    a.binfo = reinterpret_cast<const uint2*>(c->buf + c->P.off_binfo);
+    a.info = reinterpret_cast<const uint32_t*>(c->buf + c->P.off_info);
+    a.segbase = reinterpret_cast<const int32_t*>(c->buf + c->P.off_segbase);
     a.lparam = reinterpret_cast<const float*>(c->buf + c->P.off_lparam);
-    a.side = reinterpret_cast<float*>(c->buf + c->P.off_side);
     a.nx = nx; a.ny = ny; a.nz = nz; a.ncells = (int32_t)N;
     a.wp = (float)wp; a.wm = (float)wm;
     a.cp = (float)(1.0 - 0.5 * wp); a.cm = (float)(1.0 - 0.5 * wm);
@@ -361,17 +396,47 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find({c->arch, nx, ny, nz, p->layout, G.desc.bc});
-        if (it != g_tune_cache.end()) { c->block = it->second.first; c->xcd_remap = it->second.second; }
+        if (it != g_tune_cache.end()) {
+            c->block = it->second.first;
+            c->xcd_remap = it->second.second & 1;
+            c->nt = (it->second.second >> 1) & 1;
+        }
     }
-    hipError_t e;
-    const int64_t ngrid = (p->layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
-    e = launch_fill_zero(reinterpret_cast<float*>(c->buf + c->P.off_pop), ngrid * Q * c->P.stride, c->stream);
-    if (e == hipSuccess && p->layout == LBM_LAYOUT_AA)
-        e = launch_fill_zero(a.side, std::max<int64_t>(c->P.nl, 1), c->stream);
+    // moving-wall links start from the wall term alone: seed their partial
+    // values in the slots the first step pulls them from
+    std::vector<int64_t> seed_idx;
+    std::vector<float> seed_val;
+    if (c->P.nseed > 0) {
+        for (int64_t i = 0; i < c->P.nl; ++i) {
+            if (G.lsurf[i] != SURF_WALL_HI) continue;
+            const int64_t cell = G.lcell[i];
+            const int kk = G.ldir[i], k = opp(kk);
+            const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((int64_t)nx * ny));
+            const int xs = (x + D3Q19::ex[kk] + nx) % nx, ys = (y + D3Q19::ey[kk] + ny) % ny,
+                      zs = (z + D3Q19::ez[kk] + nz) % nz;
+            const int64_t solid = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
+            // two-grid pulls k from the solid neighbour's slot; AA (first step
+            // even) from the cell's own slot
+            seed_idx.push_back((int64_t)k * c->P.stride + (p->layout == LBM_LAYOUT_TWOGRID ? solid : cell));
+            seed_val.push_back(a.wterm[k]);
+        }
+    }
+    hipError_t e = hipSuccess;
+    if ((int64_t)seed_idx.size() != c->P.nseed) {
+        e = hipErrorInvalidValue;
+    } else if (c->P.nseed > 0) {
+        e = hipMemcpyAsync(c->buf + c->P.off_seed, seed_idx.data(), seed_idx.size() * 8, hipMemcpyHostToDevice,
+                           c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->buf + c->P.off_seed + c->P.nseed * 8, seed_val.data(), seed_val.size() * 4,
+                               hipMemcpyHostToDevice, c->stream);
+    }
+    if (e == hipSuccess) e = reset_state(c);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->buf + c->P.off_info, info.data(), N * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->buf + c->P.off_binfo, binfo.data(), binfo.size() * 4, hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->buf + c->P.off_segbase, segbase.data(), segbase.size() * 4, hipMemcpyHostToDevice,
+                           c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->buf + c->P.off_lparam, lparam.data(), lparam.size() * 4, hipMemcpyHostToDevice,
                            c->stream);
@@ -501,13 +566,13 @@ lbm_status lbm_totals(lbm_ctx* c, int32_t dom, double* mass, double momentum[3])
 }
 
 // checkpoint image: 4 int64 header {magic, steps, parity, cur} + populations
-// of the current grid + side buffer
+// of the current grid (the partial bounce-back values live in them)
 static const int64_t kMagic = 0x4c424d53544154;  // "LBMSTAT"
 
 lbm_status lbm_state_bytes(lbm_ctx* c, int64_t* bytes) {
     if (!c || !bytes) return fail(LBM_E_INVAL, "bad arguments");
     if (c->batch) return batch_state_bytes(c->batch, bytes);
-    *bytes = 32 + Q * c->P.stride * 4 + (c->p.layout == LBM_LAYOUT_AA ? c->P.nl * 4 : 0);
+    *bytes = 32 + Q * c->P.stride * 4;
     return LBM_OK;
 }
 
@@ -522,9 +587,6 @@ lbm_status lbm_save(lbm_ctx* c, void* host_buf, int64_t bytes) {
     char* dst = reinterpret_cast<char*>(host_buf) + 32;
     const char* pop = c->buf + c->P.off_pop + (int64_t)c->cur * Q * c->P.stride * 4;
     HIP_TRY(hipMemcpyAsync(dst, pop, Q * c->P.stride * 4, hipMemcpyDeviceToHost, c->stream), "save populations");
-    if (c->p.layout == LBM_LAYOUT_AA && c->P.nl > 0)
-        HIP_TRY(hipMemcpyAsync(dst + Q * c->P.stride * 4, c->buf + c->P.off_side, c->P.nl * 4, hipMemcpyDeviceToHost,
-                               c->stream), "save side buffer");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
     return LBM_OK;
 }
@@ -545,9 +607,6 @@ lbm_status lbm_load(lbm_ctx* c, const void* host_buf, int64_t bytes) {
     c->cur = 0;
     HIP_TRY(hipMemcpyAsync(c->buf + c->P.off_pop, src, Q * c->P.stride * 4, hipMemcpyHostToDevice, c->stream),
             "load populations");
-    if (c->p.layout == LBM_LAYOUT_AA && c->P.nl > 0)
-        HIP_TRY(hipMemcpyAsync(c->buf + c->P.off_side, src + Q * c->P.stride * 4, c->P.nl * 4, hipMemcpyHostToDevice,
-                               c->stream), "load side buffer");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
     c->steps = h[1];
     c->parity = (int)h[2];
@@ -560,45 +619,54 @@ lbm_status lbm_steps_done(lbm_ctx* c, int64_t* steps) {
     return LBM_OK;
 }
 
-lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t xcd_remap) {
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t flags) {
     if (!c || c->batch) return fail(LBM_E_INVAL, "launch shape applies to single-domain contexts");
-    if (block != 128 && block != 256 && block != 512 && block != 1024) return fail(LBM_E_INVAL, "block must be 128, 256, 512 or 1024");
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+        return fail(LBM_E_INVAL, "block must be 64, 128, 256, 512 or 1024");
+    if (flags & ~(LBM_LAUNCH_XCD_REMAP | LBM_LAUNCH_NONTEMPORAL)) return fail(LBM_E_INVAL, "unknown launch flags");
     c->block = block;
-    c->xcd_remap = xcd_remap ? 1 : 0;
+    c->xcd_remap = (flags & LBM_LAUNCH_XCD_REMAP) ? 1 : 0;
+    c->nt = (flags & LBM_LAUNCH_NONTEMPORAL) ? 1 : 0;
     return LBM_OK;
 }
 
-lbm_status lbm_get_launch(lbm_ctx* c, int32_t* block, int32_t* xcd_remap) {
+lbm_status lbm_get_launch(lbm_ctx* c, int32_t* block, int32_t* flags) {
     if (!c || c->batch) return fail(LBM_E_INVAL, "launch shape applies to single-domain contexts");
     if (block) *block = c->block;
-    if (xcd_remap) *xcd_remap = c->xcd_remap;
+    if (flags) *flags = (c->xcd_remap ? LBM_LAUNCH_XCD_REMAP : 0) | (c->nt ? LBM_LAUNCH_NONTEMPORAL : 0);
     return LBM_OK;
 }
 
 lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial) {
     if (!c || steps_per_trial < 2) return fail(LBM_E_INVAL, "bad arguments");
     if (c->batch) return batch_autotune(c->batch, steps_per_trial);
+    // the trials advance the state: keep a host copy unless it is the rest state
+    const bool at_rest = c->steps == 0;
     int64_t sb = 0;
-    lbm_status s = lbm_state_bytes(c, &sb);
-    if (s != LBM_OK) return s;
     std::vector<char> saved;
-    try {
-        saved.resize((size_t)sb);
-    } catch (const std::bad_alloc&) {
-        return fail(LBM_E_NOMEM, "host memory for the autotuner's state copy");
+    lbm_status s = LBM_OK;
+    if (!at_rest) {
+        s = lbm_state_bytes(c, &sb);
+        if (s != LBM_OK) return s;
+        try {
+            saved.resize((size_t)sb);
+        } catch (const std::bad_alloc&) {
+            return fail(LBM_E_NOMEM, "host memory for the autotuner's state copy");
+        }
+        s = lbm_save(c, saved.data(), sb);
+        if (s != LBM_OK) return s;
     }
-    s = lbm_save(c, saved.data(), sb);
-    if (s != LBM_OK) return s;
-    const int blocks[] = {128, 256, 512, 1024};
+    const int blocks[] = {64, 128, 256, 512, 1024};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");
     HIP_TRY(hipEventCreate(&e1), "event");
     float best = 1e30f;
-    int bb = c->block, br = c->xcd_remap;
+    int bb = c->block, br = c->xcd_remap, bn = c->nt;
     for (int blk : blocks)
-        for (int remap = 0; remap < 2; ++remap) {
+        for (int fl = 0; fl < 4 && s == LBM_OK; ++fl) {
             c->block = blk;
-            c->xcd_remap = remap;
+            c->xcd_remap = fl & 1;
+            c->nt = (fl >> 1) & 1;
             s = step_single(c, 2);  // warm-up (even + odd for AA)
             if (s != LBM_OK) break;
             hipEventRecord(e0, c->stream);
@@ -608,17 +676,25 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial) {
             hipEventSynchronize(e1);
             float ms = 0;
             hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) { best = ms; bb = blk; br = remap; }
+            if (ms < best) { best = ms; bb = blk; br = c->xcd_remap; bn = c->nt; }
         }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     c->block = bb;
     c->xcd_remap = br;
-    lbm_status s2 = lbm_load(c, saved.data(), sb);
+    c->nt = bn;
+    lbm_status s2 = LBM_OK;
+    if (at_rest) {
+        hipError_t e = reset_state(c);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) s2 = hip_fail(e, "reset after autotuning");
+    } else {
+        s2 = lbm_load(c, saved.data(), sb);
+    }
     if (s != LBM_OK) return s;
     if (s2 != LBM_OK) return s2;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[{c->arch, c->d.nx, c->d.ny, c->d.nz, c->p.layout, c->d.bc}] = {bb, br};
+    g_tune_cache[{c->arch, c->d.nx, c->d.ny, c->d.nz, c->p.layout, c->d.bc}] = {bb, br | (bn << 1)};
     return LBM_OK;
 }
 

@@ -64,7 +64,7 @@ lbm_status build_domain(const lbm_domain_desc& din, DomainGeo& out, std::string&
         if (!per && n[a] < 3) { err = "a walled axis needs at least 3 cells"; return LBM_E_INVAL; }
     }
     const int64_t N = (int64_t)d.nx * d.ny * d.nz;
-    if (N >= (int64_t)1 << 31) { err = "more than 2^31 - 1 cells"; return LBM_E_INVAL; }
+    if (N > (int64_t)1 << 30) { err = "more than 2^30 cells in one domain"; return LBM_E_INVAL; }
     if (d.bc < LBM_BC_SBB || d.bc > LBM_BC_BOUZIDI) { err = "unknown boundary scheme"; return LBM_E_INVAL; }
     if (d.n_spheres < 0 || (d.n_spheres > 0 && !d.spheres)) { err = "bad sphere array"; return LBM_E_INVAL; }
     for (int a = 0; a < 3; ++a)

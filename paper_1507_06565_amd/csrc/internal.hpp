@@ -28,11 +28,16 @@ struct DomainGeo {
 lbm_status build_domain(const lbm_domain_desc& d, DomainGeo& out, std::string& err);
 
 // ----------------------------------------------------------- device layout --
-// info[c]: INFO_SOLID, INFO_FLUID (no links) or the boundary-cell id b >= 0;
-// binfo[b] = {mask, base}: bit (k-1) of mask set if (c, k) is a link, the
-// link's record is lparam[base + popcount(mask & ((1 << (k-1)) - 1))].
-constexpr int32_t INFO_SOLID = -2;
-constexpr int32_t INFO_FLUID = -1;
+// One 32-bit word per cell:
+//   CELL_SOLID_WORD (all ones)  solid cell, not updated;
+//   otherwise bits 0..17 are the link mask (bit k-1 set if x + e_k is solid)
+//   and bits 18..31 the offset of the cell's first link from the first link
+//   of its 512-cell segment; segbase[c >> 9] holds that segment's first link.
+//   A segment has at most 512 * 18 = 9216 links, so the offset fits 14 bits.
+// Link i of cell c (in increasing k) has its record at lparam[first + i].
+constexpr uint32_t CELL_SOLID_WORD = 0xFFFFFFFFu;
+constexpr int SEG_SHIFT = 9;
+constexpr uint32_t LINK_MASK_BITS = 0x3FFFFu;
 
 enum Layout : int { L_TWOGRID = 0, L_AA = 1 };
 enum Parity : int { P_EVEN = 0, P_ODD = 1 };
@@ -41,10 +46,12 @@ struct SweepArgs {
     float* A;        // populations (two-grid: source grid; AA: the only grid)
     float* B;        // two-grid destination grid (unused for AA)
     int64_t stride;  // floats between consecutive population arrays
-    const int32_t* info;
-    const uint2* binfo;
-    const float* lparam;  // CLI: kappa; Bouzidi: q; NaN: moving-wall bounce-back
-    float* side;          // AA: post-collision value of each link's unknown population
+    float* pa[Q];    // A + k*stride (uniform bases, filled per launch)
+    float* pb[Q];    // B + k*stride
+    const uint32_t* info;
+    const int32_t* segbase;
+    const float* lparam;  // CLI: kappa; Bouzidi: q; NaN: moving-wall bounce-back;
+                          // padded with Q entries so that rank lookups stay in bounds
     int32_t nx, ny, nz, ncells;
     float wp, wm;         // omega+, omega-
     float cp, cm;         // 1 - omega+/2, 1 - omega-/2
@@ -52,6 +59,7 @@ struct SweepArgs {
     float F[3];
     float wterm[Q];       // 6 w_k rho0 e_k.u_w for the moving wall
     int32_t xcd_remap;
+    int32_t nt;           // non-temporal hints on the aligned streams
 };
 
 hipError_t launch_sweep(const SweepArgs& a, int layout, int parity, int bc, int block, hipStream_t s);
@@ -59,7 +67,7 @@ hipError_t launch_sweep(const SweepArgs& a, int layout, int parity, int bc, int 
 struct MomentArgs {
     const float* A;
     int64_t stride;
-    const int32_t* info;
+    const uint32_t* info;
     int32_t nx, ny, nz;
     int32_t layout, parity;  // parity of the last step taken (AA); -1: no step yet
     double rho0;
@@ -74,5 +82,8 @@ hipError_t launch_plane_sums(const MomentArgs& a, int axis, double* out, hipStre
 hipError_t launch_fields(const MomentArgs& a, int64_t c0, int64_t n, double* out, hipStream_t s);
 
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+
+// p[idx[i]] = val[i] for i < n (seeding the moving-wall partial values)
+hipError_t launch_scatter(float* p, const int64_t* idx, const float* val, int64_t n, hipStream_t s);
 
 }  // namespace lbm

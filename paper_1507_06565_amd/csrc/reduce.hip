@@ -29,7 +29,7 @@ __device__ __forceinline__ float post(const MomentArgs& a, int k, int c, int x, 
 
 __device__ __forceinline__ bool cell_moments(const MomentArgs& a, int c, double& rho, double& ux, double& uy,
                                              double& uz) {
-    if (a.info[c] == INFO_SOLID) return false;
+    if (a.info[c] == CELL_SOLID_WORD) return false;
     const int x = c % a.nx, t = c / a.nx, y = t % a.ny, z = t / a.ny;
     double s = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll

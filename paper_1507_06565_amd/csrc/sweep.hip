@@ -8,20 +8,24 @@
 // shifts g = f - w rho0.  The pass is HBM-bound: 19 loads + 19 stores of 4 B
 // per fluid cell, plus a 4 B cell-info load; solid cells return at once.
 //
-// Boundary handling is fused into the sweep: a fluid cell x with a link k
-// (x + e_k solid) rebuilds its unknown population kbar = opp(k) as
-//     g_kbar(x, t+1) = c1 gt_k(x) + c0 gt_k(x - e_k) + cb gt_kbar(x) [+ wall]
-// where gt are the post-collision values of step t.  gt_k(x - e_k) is the
-// value x pulls for direction k anyway; gt_k(x) and gt_kbar(x) are x's own
-// values of the previous step, which each layout keeps where nobody else
-// writes them during the step:
-//   two-grid   : source grid A[k][x], A[kbar][x]
-//   AA, even   : gt_k(x) sits in the solid neighbour's slot A[k][x + e_k]
-//                (written by x in the previous odd step, read by nobody else);
-//                gt_kbar(x) in the per-link side buffer
-//   AA, odd    : gt_k(x) in x's own slot A[kbar][x] (no other cell reads or
-//                writes it in an odd step); gt_kbar(x) in the side buffer.
-// The arithmetic is the same in every layout, so they agree bit for bit.
+// Boundary handling is fused into the sweep.  A fluid cell x with a link kk
+// (x + e_kk solid) rebuilds its unknown population k = opp(kk) as
+//     g_k(x, t+1) = c1 gt_kk(x) + c0 gt_kk(x - e_kk) + cb gt_k(x) [+ wall]
+// (eq. (noslip), eq. (CLI), or Bouzidi), gt being post-collision values of
+// step t.  At the end of step t the cell itself owns gt_kk(x) and gt_k(x), so
+// it stores the partial value P = c1 gt_kk(x) + cb gt_k(x) [+ wall] straight
+// into the slot it will pull direction k from at step t+1 -- a slot that
+// would otherwise stream out of the solid and that no other cell reads or
+// writes:
+//   two-grid   : destination grid, solid neighbour's slot B[k][x + e_kk]
+//   AA, even   : A[kk][x + e_kk]   (the odd step pulls k from there)
+//   AA, odd    : A[k][x]           (the even step pulls k from there)
+// At step t+1 the plain pull returns P and the cell adds c0 gt_kk(x - e_kk),
+// which is the value it pulls for direction kk.  The only per-link data read
+// is the link coefficient; c0 = 0 (simple bounce-back, moving wall, a second
+// node that is not fluid, Bouzidi with q >= 1/2) needs nothing at all at the
+// start of the step.  Arithmetic is identical in every layout, so the
+// layouts agree bit for bit.
 //
 // AA state locations: after an even step gt_k(x) is stored at A[kbar][x];
 // after an odd step at A[k][x + e_k].  An even step reads A[k][x] and writes
@@ -44,9 +48,14 @@ __device__ __forceinline__ int remap_block(int b, int nblocks) {
     return b;
 }
 
+// (c1, c0, cb) of a link from its coefficient word: CLI stores kappa =
+// (1 - 2q)/(1 + 2q), Bouzidi stores q, NaN marks a moving-wall link (simple
+// bounce-back plus the wall term).
 template <int BC>
 __device__ __forceinline__ void bb_coeffs(float prm, float& c1, float& c0, float& cb) {
-    if (BC == LBM_BC_CLI) {
+    if (prm != prm) {
+        c1 = 1.0f; c0 = 0.0f; cb = 0.0f;
+    } else if (BC == LBM_BC_CLI) {
         c1 = 1.0f; c0 = prm; cb = -prm;
     } else if (BC == LBM_BC_BOUZIDI) {
         if (prm < 0.5f) {
@@ -103,127 +112,162 @@ __device__ __forceinline__ void collide(float (&g)[Q], const SweepArgs& a) {
     }
 }
 
-template <int LAYOUT, int PARITY, int BC, int BLOCK>
+template <bool NT>
+__device__ __forceinline__ float ld(const float* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st(float* p, float v) {
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// ROW: the workgroup size divides nx, so a workgroup covers part of one x-row
+// and y, z are uniform (scalar) per workgroup.  NT: non-temporal hints on the
+// streams whose wavefront accesses are 256-byte aligned.
+template <int LAYOUT, int PARITY, int BC, int BLOCK, bool ROW, bool NT>
 __global__ void __launch_bounds__(BLOCK) k_sweep(SweepArgs a) {
     int b = blockIdx.x;
     if (a.xcd_remap) b = remap_block(b, gridDim.x);
-    const int c = b * BLOCK + threadIdx.x;
-    if (c >= a.ncells) return;
-    const int inf = a.info[c];
-    if (inf == INFO_SOLID) return;
-
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int x = c % nx;
-    const int t = c / nx;
-    const int y = t % ny;
-    const int z = t / ny;
-    const int X[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
-    const int Y[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
-    const int Z[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
-    // linear index of x + (dx, dy, dz)
-#define NB(dx, dy, dz) (X[(dx) + 1] + nx * (Y[(dy) + 1] + ny * Z[(dz) + 1]))
-
-    float* __restrict__ A = a.A;
-    const int64_t S = a.stride;
-
-    uint32_t mask = 0;
-    int base = 0;
-    if (inf >= 0) {
-        const uint2 bi = a.binfo[inf];
-        mask = bi.x;
-        base = (int)bi.y;
+    int c, x, y, z;
+    if (ROW) {
+        const int first = b * BLOCK;          // uniform
+        const int row = first / nx;           // uniform
+        y = row % ny;
+        z = row / ny;
+        x = first - row * nx + threadIdx.x;
+        c = first + threadIdx.x;
+    } else {
+        c = b * BLOCK + threadIdx.x;
+        if (c >= a.ncells) return;
+        x = c % nx;
+        const int t = c / nx;
+        y = t % ny;
+        z = t / ny;
     }
+    const unsigned X[3] = {(unsigned)(x == 0 ? nx - 1 : x - 1), (unsigned)x, (unsigned)(x == nx - 1 ? 0 : x + 1)};
+    const unsigned Y[3] = {(unsigned)(y == 0 ? ny - 1 : y - 1), (unsigned)y, (unsigned)(y == ny - 1 ? 0 : y + 1)};
+    const unsigned Z[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1), (unsigned)z, (unsigned)(z == nz - 1 ? 0 : z + 1)};
+    const unsigned unx = (unsigned)nx, uny = (unsigned)ny;
+    const unsigned uc = (unsigned)c;
+    // linear index of x + (dx, dy, dz); all indices are below 2^31
+#define NB(dx, dy, dz) (X[(dx) + 1] + unx * (Y[(dy) + 1] + uny * Z[(dz) + 1]))
 
-    // 1) streaming: pull every population that does not come out of a solid
+    // Addressing: population k of cell i is at byte offset 4*i from the
+    // array base A + k*stride (uniform); 4*i fits 32 bits (the host limits a
+    // domain to 2^30 cells), so loads use a scalar base + 32-bit offset.
+#define AT(bases, k, idx) (*(float*)((char*)(bases)[k] + ((uint32_t)(idx) << 2)))
+
+    // 1) streaming: the cell word and all 19 pulls are issued together; the
+    //    empty asm pins the pulls ahead of the solid-cell branch, so a
+    //    wavefront waits for memory once
+    const uint32_t inf = a.info[c];
     float g[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        const int kb = opp(k);
-        const bool link = (k != 0) && (mask & (1u << (kb - 1)));
-        float v = 0.0f;
-        if (!link) {
-            if (LAYOUT == L_TWOGRID)
-                v = A[k * S + NB(-L::ex[k], -L::ey[k], -L::ez[k])];
-            else if (PARITY == P_EVEN)
-                v = A[k * S + c];
-            else
-                v = A[kb * S + NB(-L::ex[k], -L::ey[k], -L::ez[k])];
-        }
-        g[k] = v;
+        if (LAYOUT == L_TWOGRID)
+            g[k] = AT(a.pa, k, NB(-L::ex[k], -L::ey[k], -L::ez[k]));
+        else if (PARITY == P_EVEN)
+            g[k] = ld<NT>(&AT(a.pa, k, uc));
+        else
+            g[k] = AT(a.pa, opp(k), NB(-L::ex[k], -L::ey[k], -L::ez[k]));
     }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) asm volatile("" ::"v"(g[k]));
+    if (inf == CELL_SOLID_WORD) return;
+    const uint32_t mask = inf & LINK_MASK_BITS;
 
-    // 2) bounce-back of the populations that would come out of the solid
+    // 2) links: the pulled value of an unknown population is the partial
+    //    value P stored last step; add c0 times the second node's value
+    float prm[Q];
     if (mask) {
-        float h[Q];
+        const int base = a.segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
+        // every coefficient load is issued before any is used, without
+        // branches: for a direction that is not a link the rank points at a
+        // neighbouring record (the array is padded), whose value is unused
+        const char* lp = (const char*)a.lparam;
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
-            const int kk = opp(k);  // link direction: x + e_kk is solid
-            h[k] = g[k];
+            const int kk = opp(k);
+            const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
+            prm[k] = *(const float*)(lp + (li << 2));
+        }
+        // in place: g[kk] is read only when (x, k) is not itself a link, so
+        // it still holds its pulled value
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const int kk = opp(k);
             if (mask & (1u << (kk - 1))) {
-                const int li = base + __popc(mask & ((1u << (kk - 1)) - 1u));
-                const float prm = a.lparam[li];
-                float own_kk, own_k;
-                if (LAYOUT == L_TWOGRID) {
-                    own_kk = A[kk * S + c];
-                    own_k = A[k * S + c];
-                } else if (PARITY == P_EVEN) {
-                    own_kk = A[kk * S + NB(L::ex[kk], L::ey[kk], L::ez[kk])];
-                    own_k = a.side[li];
-                } else {
-                    own_kk = A[k * S + c];
-                    own_k = a.side[li];
-                }
-                float c1, c0, cb, wt = 0.0f;
-                if (prm != prm) {  // moving wall: simple bounce-back + Ladd term
-                    c1 = 1.0f; c0 = 0.0f; cb = 0.0f; wt = a.wterm[k];
-                } else {
-                    bb_coeffs<BC>(prm, c1, c0, cb);
-                }
-                h[k] = c1 * own_kk + c0 * g[kk] + cb * own_k + wt;
+                float c1, c0, cb;
+                bb_coeffs<BC>(prm[k], c1, c0, cb);
+                if (c0 != 0.0f) g[k] += c0 * g[kk];
             }
         }
-#pragma unroll
-        for (int k = 1; k < Q; ++k) g[k] = h[k];
     }
 
     // 3) collision
     collide(g, a);
 
     // 4) store
-    float* __restrict__ D = (LAYOUT == L_TWOGRID) ? a.B : A;
+    float* const* D = (LAYOUT == L_TWOGRID) ? a.pb : a.pa;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         if (LAYOUT == L_TWOGRID)
-            D[k * S + c] = g[k];
+            st<NT>(&AT(D, k, uc), g[k]);
         else if (PARITY == P_EVEN)
-            D[opp(k) * S + c] = g[k];
+            st<NT>(&AT(D, opp(k), uc), g[k]);
         else
-            D[k * S + NB(L::ex[k], L::ey[k], L::ez[k])] = g[k];
+            AT(D, k, NB(L::ex[k], L::ey[k], L::ez[k])) = g[k];
     }
-    if (LAYOUT == L_AA && mask) {
+    // 5) partial bounce-back values for the next step
+    if (mask) {
 #pragma unroll
-        for (int kk = 1; kk < Q; ++kk) {
+        for (int k = 1; k < Q; ++k) {
+            const int kk = opp(k);
             if (mask & (1u << (kk - 1))) {
-                const int li = base + __popc(mask & ((1u << (kk - 1)) - 1u));
-                a.side[li] = g[opp(kk)];
+                float c1, c0, cb;
+                bb_coeffs<BC>(prm[k], c1, c0, cb);
+                const float P = c1 * g[kk] + cb * g[k] + (prm[k] != prm[k] ? a.wterm[k] : 0.0f);
+                if (LAYOUT == L_TWOGRID)
+                    AT(D, k, NB(L::ex[kk], L::ey[kk], L::ez[kk])) = P;
+                else if (PARITY == P_EVEN)
+                    AT(D, kk, NB(L::ex[kk], L::ey[kk], L::ez[kk])) = P;
+                else
+                    AT(D, k, uc) = P;
             }
         }
     }
+#undef AT
 #undef NB
+}
+
+template <int LAYOUT, int PARITY, int BC, int BLOCK>
+hipError_t launch4(const SweepArgs& a, hipStream_t s) {
+    const unsigned nb = (unsigned)(((int64_t)a.ncells + BLOCK - 1) / BLOCK);
+    const bool row = (a.nx % BLOCK) == 0;
+    if (row && a.nt)
+        k_sweep<LAYOUT, PARITY, BC, BLOCK, true, true><<<nb, BLOCK, 0, s>>>(a);
+    else if (row)
+        k_sweep<LAYOUT, PARITY, BC, BLOCK, true, false><<<nb, BLOCK, 0, s>>>(a);
+    else if (a.nt)
+        k_sweep<LAYOUT, PARITY, BC, BLOCK, false, true><<<nb, BLOCK, 0, s>>>(a);
+    else
+        k_sweep<LAYOUT, PARITY, BC, BLOCK, false, false><<<nb, BLOCK, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 template <int LAYOUT, int PARITY, int BC>
 hipError_t launch3(const SweepArgs& a, int block, hipStream_t s) {
-    const int64_t nb64 = ((int64_t)a.ncells + block - 1) / block;
-    const unsigned nb = (unsigned)nb64;
     switch (block) {
-        case 128: k_sweep<LAYOUT, PARITY, BC, 128><<<nb, 128, 0, s>>>(a); break;
-        case 256: k_sweep<LAYOUT, PARITY, BC, 256><<<nb, 256, 0, s>>>(a); break;
-        case 512: k_sweep<LAYOUT, PARITY, BC, 512><<<nb, 512, 0, s>>>(a); break;
-        case 1024: k_sweep<LAYOUT, PARITY, BC, 1024><<<nb, 1024, 0, s>>>(a); break;
+        case 64: return launch4<LAYOUT, PARITY, BC, 64>(a, s);
+        case 128: return launch4<LAYOUT, PARITY, BC, 128>(a, s);
+        case 256: return launch4<LAYOUT, PARITY, BC, 256>(a, s);
+        case 512: return launch4<LAYOUT, PARITY, BC, 512>(a, s);
+        case 1024: return launch4<LAYOUT, PARITY, BC, 1024>(a, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int LAYOUT, int PARITY>
@@ -242,7 +286,18 @@ __global__ void k_fill_zero(float* p, int64_t n) {
     for (int64_t j = i; j < n; j += stride) p[j] = 0.0f;
 }
 
+__global__ void k_scatter(float* p, const int64_t* idx, const float* val, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[idx[i]] = val[i];
+}
+
 }  // namespace
+
+hipError_t launch_scatter(float* p, const int64_t* idx, const float* val, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_scatter<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, idx, val, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_sweep(const SweepArgs& a, int layout, int parity, int bc, int block, hipStream_t s) {
     if (layout == L_TWOGRID) return launch2<L_TWOGRID, P_EVEN>(a, bc, block, s);

@@ -173,8 +173,9 @@ class Context:
         check(lib.lbm_load(self.ptr, image.ctypes.data, image.size), "lbm_load")
 
     # --- launch configuration
-    def set_launch(self, block, xcd_remap=1):
-        check(lib.lbm_set_launch(self.ptr, block, xcd_remap), "lbm_set_launch")
+    def set_launch(self, block, flags=1):
+        """flags: 1 = XCD-contiguous tiles, 2 = non-temporal aligned streams."""
+        check(lib.lbm_set_launch(self.ptr, block, flags), "lbm_set_launch")
 
     def get_launch(self):
         b, r = C.c_int32(), C.c_int32()

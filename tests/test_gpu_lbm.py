@@ -32,13 +32,13 @@ def rel_l2(u, ref, fluid):
     return float(np.linalg.norm((u - ref)[m]) / np.linalg.norm(ref[m]))
 
 
-def gpu_run(dom, params, steps, layout="twogrid", block=None, remap=None):
+def gpu_run(dom, params, steps, layout="twogrid", block=None, flags=None):
     lbm = _lbm()
     p = W.Params(**{**params.__dict__, "layout": layout})
     g = lbm.Geometry(dom)
     ctx = lbm.Context(g, p)
     if block is not None:
-        ctx.set_launch(block, remap)
+        ctx.set_launch(block, flags)
     ctx.step(steps)
     rho, u = ctx.fields()
     return ctx, rho, u
@@ -126,15 +126,18 @@ def test_aa_equals_twogrid_bitwise():
 
 def test_launch_shapes_bitwise():
     say("test_launch_shapes_bitwise")
-    d = small_spheres(seed=5, bc="bouzidi")
+    # nx = 128: workgroups of 64 and 128 cells cover whole rows (row mapping),
+    # larger ones straddle rows (generic mapping); both must agree
+    d = small_spheres(seed=5, bc="bouzidi", shape=(128, 20, 30))
     p = W.Params(collision="trt", tau_plus=0.7, magic_lambda=3 / 16, force=(2e-5, 0, 0))
     base = None
-    for block in (128, 256, 512, 1024):
-        for remap in (0, 1):
-            _, _, u = gpu_run(d, p, 40, "aa", block, remap)
-            if base is None:
-                base = u
-            assert np.array_equal(u, base), (block, remap)
+    for layout in ("aa", "twogrid"):
+        for block in (64, 128, 256, 512, 1024):
+            for flags in (0, 1, 2, 3):
+                _, _, u = gpu_run(d, p, 41, layout, block, flags)
+                if base is None:
+                    base = u
+                assert np.array_equal(u, base), (layout, block, flags)
 
 
 def test_split_runs_and_restart_bitwise():
@@ -204,3 +207,54 @@ def test_c1_full_size_parity():
     rs, _, rpor = oracle.plane_profile(ref.velocity(), ref.fluid(), 2, 0)
     assert np.array_equal(por, rpor)
     assert np.linalg.norm(s - rs) <= REL_L2 * np.linalg.norm(rs)
+
+
+# ------------------------------------------------------------------ C2 ---
+
+def test_c2_full_size_sampled_windows():
+    """C2 at full size (512x256x1024, AA, CLI, TRT 3/16, tau 0.7) in the launch
+    configuration the benchmark uses: 8 steps from rest, then sampled cells
+    against oracle windows whose edge is more than 8 cells away (the light
+    cone of 8 steps); also the bed porosity and plane porosity profile."""
+    say("test_c2_full_size_sampled_windows")
+    lbm = _lbm()
+    d, p, eps = W.large_c2()
+    assert abs(eps - 0.45) <= 0.01
+    g = lbm.Geometry(d)
+    ctx = lbm.Context(g, p)
+    ctx.autotune(4)
+    nsteps = 8
+    ctx.step(nsteps)
+    _, u = ctx.fields()
+    _, _, por = ctx.average_profile(0, 2, 0)
+    fl = oracle.flags(d)
+    assert np.array_equal(por, (fl == 0).sum(axis=(1, 2)) / (d.nx * d.ny))
+    geo = (fl,) + oracle.links(d, fl)
+    rng = np.random.default_rng(42)
+    h = nsteps + 2
+    w = 2 * h + 6
+    num = den = 0.0
+    checked = 0
+    for i in range(16):
+        # half of the windows straddle the bed surface (z ~ 512)
+        cz = int(rng.integers(490, 530)) if i % 2 else int(rng.integers(h + 1, d.nz - h - 7))
+        org = (int(rng.integers(0, d.nx)), int(rng.integers(0, d.ny)), cz - h)
+        sim = oracle.Sim(d, p, window=(org, (w, w, w)), geometry=geo)
+        sim.step(nsteps)
+        uw, fw = sim.velocity(), sim.fluid()
+        for zz in range(h, w - h):
+            for yy in range(h, w - h):
+                for xx in range(h, w - h):
+                    if not fw[zz, yy, xx]:
+                        continue
+                    gx, gy, gz = (org[0] + xx) % d.nx, (org[1] + yy) % d.ny, org[2] + zz
+                    ref = uw[:, zz, yy, xx]
+                    got = u[:, gz, gy, gx]
+                    assert np.all(np.isfinite(ref))
+                    num += float(((got - ref) ** 2).sum())
+                    den += float((ref ** 2).sum())
+                    checked += 1
+    e = (num / den) ** 0.5
+    say("C2 sampled cells", checked, "rel L2", e)
+    assert checked > 1000
+    assert e <= REL_L2
