@@ -24,6 +24,8 @@ lbm_status batch_state_bytes(BatchCtx* b, int64_t* bytes);
 lbm_status batch_save(BatchCtx* b, void* host, int64_t bytes, int64_t steps);
 lbm_status batch_load(BatchCtx* b, const void* host, int64_t bytes);
 lbm_status batch_autotune(BatchCtx* b, int32_t steps_per_trial);
+lbm_status batch_set_launch(BatchCtx* b, int32_t block, int32_t W);
+lbm_status batch_get_launch(BatchCtx* b, int32_t* block, int32_t* W);
 void batch_destroy(BatchCtx* b);
 
 // error text for the calling thread (defined with the C ABI)

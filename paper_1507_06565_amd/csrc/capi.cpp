@@ -164,6 +164,27 @@ lbm_status plane_sums(lbm_ctx* c, int axis, std::vector<double>& out) {
     return LBM_OK;
 }
 
+}  // namespace
+
+CellConsts lbm::make_consts(const lbm_params& p, double wp, double wm, const double* wall_velocity) {
+    CellConsts k{};
+    k.wp = (float)wp;
+    k.wm = (float)wm;
+    k.cp = (float)(1.0 - 0.5 * wp);
+    k.cm = (float)(1.0 - 0.5 * wm);
+    k.rho0 = (float)p.rho0;
+    k.inv_rho0 = (float)(1.0 / p.rho0);
+    for (int i = 0; i < 3; ++i) k.F[i] = (float)p.force[i];
+    for (int j = 0; j < Q; ++j) {
+        const double eu = D3Q19::ex[j] * wall_velocity[0] + D3Q19::ey[j] * wall_velocity[1] +
+                          D3Q19::ez[j] * wall_velocity[2];
+        k.wterm[j] = (float)(6.0 * weight(j) * p.rho0 * eu);
+    }
+    return k;
+}
+
+namespace {
+
 int flow_axis(const lbm_params& p) {
     int a = 0;
     for (int i = 1; i < 3; ++i)
@@ -333,65 +354,24 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
     }
     // host images of the cell info, boundary-cell records and link parameters
     const int64_t N = c->P.N;
-    std::vector<uint32_t> info((size_t)N);
-    for (int64_t i = 0; i < N; ++i) info[i] = G.flags[i] == CELL_FLUID ? 0u : CELL_SOLID_WORD;
-    const int64_t nseg = (N >> SEG_SHIFT) + 1;
-    std::vector<int32_t> segbase((size_t)nseg, 0);
-    std::vector<float> lparam((size_t)(c->P.nl + Q), 0.0f);
-    const bool moving = G.desc.wall_hi_velocity[0] != 0.0 || G.desc.wall_hi_velocity[1] != 0.0 ||
-                        G.desc.wall_hi_velocity[2] != 0.0;
-    const int nx = G.desc.nx, ny = G.desc.ny, nz = G.desc.nz;
+    DeviceImages im;
     {
-        // first link of every segment (links are sorted by cell)
-        int64_t li = 0;
-        for (int64_t sg = 0; sg < nseg; ++sg) {
-            while (li < c->P.nl && (G.lcell[li] >> SEG_SHIFT) < sg) ++li;
-            segbase[sg] = (int32_t)li;
+        std::string err;
+        lbm_status st = build_images(G, p->layout, c->P.stride, make_consts(*p, wp, wm, G.desc.wall_hi_velocity), im,
+                                     err);
+        if (st != LBM_OK) {
+            delete c;
+            return fail(st, err);
         }
     }
-    for (int64_t i = 0; i < c->P.nl; ++i) {
-        const int64_t cell = G.lcell[i];
-        const int k = G.ldir[i];
-        if (i == 0 || cell != G.lcell[i - 1]) {
-            const int64_t off = i - segbase[cell >> SEG_SHIFT];
-            if (off < 0 || off >= (1 << 14)) {
-                delete c;
-                return fail(LBM_E_INVAL, "internal: link offset outside its segment");
-            }
-            info[cell] = (uint32_t)off << 18;
-        }
-        info[cell] |= 1u << (k - 1);
-        // second fluid node x - e_k decides the interpolation fallback
-        const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((int64_t)nx * ny));
-        int x2 = x - D3Q19::ex[k], y2 = y - D3Q19::ey[k], z2 = z - D3Q19::ez[k];
-        x2 = (x2 + nx) % nx; y2 = (y2 + ny) % ny; z2 = (z2 + nz) % nz;
-        const bool f2 = G.flags[x2 + (int64_t)nx * (y2 + (int64_t)ny * z2)] == CELL_FLUID;
-        const double q = G.lq[i];
-        float prm = 0.0f;
-        if (moving && G.lsurf[i] == SURF_WALL_HI) {
-            prm = std::numeric_limits<float>::quiet_NaN();
-        } else if (G.desc.bc == LBM_BC_CLI) {
-            prm = f2 ? (float)((1.0 - 2.0 * q) / (1.0 + 2.0 * q)) : 0.0f;
-        } else if (G.desc.bc == LBM_BC_BOUZIDI) {
-            prm = (q < 0.5 && !f2) ? 0.5f : (float)q;
-        }
-        lparam[i] = prm;
-    }
+    const int nx = G.desc.nx, ny = G.desc.ny, nz = G.desc.nz;
     SweepArgs& a = c->sa;
     a.stride = c->P.stride;
     a.info = reinterpret_cast<const uint32_t*>(c->buf + c->P.off_info);
     a.segbase = reinterpret_cast<const int32_t*>(c->buf + c->P.off_segbase);
     a.lparam = reinterpret_cast<const float*>(c->buf + c->P.off_lparam);
     a.nx = nx; a.ny = ny; a.nz = nz; a.ncells = (int32_t)N;
-    a.wp = (float)wp; a.wm = (float)wm;
-    a.cp = (float)(1.0 - 0.5 * wp); a.cm = (float)(1.0 - 0.5 * wm);
-    a.rho0 = (float)p->rho0; a.inv_rho0 = (float)(1.0 / p->rho0);
-    for (int i = 0; i < 3; ++i) a.F[i] = (float)p->force[i];
-    for (int k = 0; k < Q; ++k) {
-        const double eu = D3Q19::ex[k] * G.desc.wall_hi_velocity[0] + D3Q19::ey[k] * G.desc.wall_hi_velocity[1] +
-                          D3Q19::ez[k] * G.desc.wall_hi_velocity[2];
-        a.wterm[k] = (float)(6.0 * weight(k) * p->rho0 * eu);
-    }
+    a.k = make_consts(*p, wp, wm, G.desc.wall_hi_velocity);
     // launch configuration from the tuning cache, if any
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -402,26 +382,12 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
             c->nt = (it->second.second >> 1) & 1;
         }
     }
-    // moving-wall links start from the wall term alone: seed their partial
-    // values in the slots the first step pulls them from
-    std::vector<int64_t> seed_idx;
-    std::vector<float> seed_val;
-    if (c->P.nseed > 0) {
-        for (int64_t i = 0; i < c->P.nl; ++i) {
-            if (G.lsurf[i] != SURF_WALL_HI) continue;
-            const int64_t cell = G.lcell[i];
-            const int kk = G.ldir[i], k = opp(kk);
-            const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((int64_t)nx * ny));
-            const int xs = (x + D3Q19::ex[kk] + nx) % nx, ys = (y + D3Q19::ey[kk] + ny) % ny,
-                      zs = (z + D3Q19::ez[kk] + nz) % nz;
-            const int64_t solid = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
-            // two-grid pulls k from the solid neighbour's slot; AA (first step
-            // even) from the cell's own slot
-            seed_idx.push_back((int64_t)k * c->P.stride + (p->layout == LBM_LAYOUT_TWOGRID ? solid : cell));
-            seed_val.push_back(a.wterm[k]);
-        }
-    }
     hipError_t e = hipSuccess;
+    const auto& seed_idx = im.seed_idx;
+    const auto& seed_val = im.seed_val;
+    const auto& info = im.info;
+    const auto& segbase = im.segbase;
+    const auto& lparam = im.lparam;
     if ((int64_t)seed_idx.size() != c->P.nseed) {
         e = hipErrorInvalidValue;
     } else if (c->P.nseed > 0) {
@@ -597,12 +563,12 @@ lbm_status lbm_load(lbm_ctx* c, const void* host_buf, int64_t bytes) {
     if (s != LBM_OK) return s;
     if (!host_buf || bytes < need) return fail(LBM_E_INVAL, "state image too small");
     const int64_t* h = reinterpret_cast<const int64_t*>(host_buf);
-    if (h[0] != kMagic) return fail(LBM_E_INVAL, "not a state image");
     if (c->batch) {
         s = batch_load(c->batch, host_buf, bytes);
         if (s == LBM_OK) c->steps = h[1];
         return s;
     }
+    if (h[0] != kMagic) return fail(LBM_E_INVAL, "not a state image");
     const char* src = reinterpret_cast<const char*>(host_buf) + 32;
     c->cur = 0;
     HIP_TRY(hipMemcpyAsync(c->buf + c->P.off_pop, src, Q * c->P.stride * 4, hipMemcpyHostToDevice, c->stream),
@@ -696,6 +662,16 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[{c->arch, c->d.nx, c->d.ny, c->d.nz, c->p.layout, c->d.bc}] = {bb, br | (bn << 1)};
     return LBM_OK;
+}
+
+lbm_status lbm_batch_set_launch(lbm_ctx* c, int32_t block, int32_t workgroups_per_domain) {
+    if (!c || !c->batch) return fail(LBM_E_INVAL, "not a batched context");
+    return batch_set_launch(c->batch, block, workgroups_per_domain);
+}
+
+lbm_status lbm_batch_get_launch(lbm_ctx* c, int32_t* block, int32_t* workgroups_per_domain) {
+    if (!c || !c->batch) return fail(LBM_E_INVAL, "not a batched context");
+    return batch_get_launch(c->batch, block, workgroups_per_domain);
 }
 
 void lbm_destroy(lbm_ctx* c) {

@@ -1,0 +1,247 @@
+// Fused stream + collide sweep of the D3Q19 TRT lattice Boltzmann method
+// (Sec. 2.1, eqs. (LBM), (TRT), (TRT2), (equilibrium), (Macro), (collision),
+// (streaming)) with interpolated bounce-back at the solid surfaces (Sec. 2.2,
+// eqs. (noslip), (CLI)), for gfx950.
+//
+// One thread per cell, x fastest, so a 64-wide wavefront reads and writes
+// 64 consecutive floats of each population array.  Populations are FP32
+// shifts g = f - w rho0.  The pass is HBM-bound: 19 loads + 19 stores of 4 B
+// per fluid cell, plus a 4 B cell-info load; solid cells return at once.
+//
+// Boundary handling is fused into the sweep.  A fluid cell x with a link kk
+// (x + e_kk solid) rebuilds its unknown population k = opp(kk) as
+//     g_k(x, t+1) = c1 gt_kk(x) + c0 gt_kk(x - e_kk) + cb gt_k(x) [+ wall]
+// (eq. (noslip), eq. (CLI), or Bouzidi), gt being post-collision values of
+// step t.  At the end of step t the cell itself owns gt_kk(x) and gt_k(x), so
+// it stores the partial value P = c1 gt_kk(x) + cb gt_k(x) [+ wall] straight
+// into the slot it will pull direction k from at step t+1 -- a slot that
+// would otherwise stream out of the solid and that no other cell reads or
+// writes:
+//   two-grid   : destination grid, solid neighbour's slot B[k][x + e_kk]
+//   AA, even   : A[kk][x + e_kk]   (the odd step pulls k from there)
+//   AA, odd    : A[k][x]           (the even step pulls k from there)
+// At step t+1 the plain pull returns P and the cell adds c0 gt_kk(x - e_kk),
+// which is the value it pulls for direction kk.  The only per-link data read
+// is the link coefficient; c0 = 0 (simple bounce-back, moving wall, a second
+// node that is not fluid, Bouzidi with q >= 1/2) needs nothing at all at the
+// start of the step.  Arithmetic is identical in every layout, so the
+// layouts agree bit for bit.
+//
+// AA state locations: after an even step gt_k(x) is stored at A[kbar][x];
+// after an odd step at A[k][x + e_k].  An even step reads A[k][x] and writes
+// A[kbar][x]; an odd step reads A[kbar][x - e_k] and writes A[k][x + e_k].
+// Every slot is read and written by one thread only.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace lbm {
+
+using L = D3Q19;
+
+// (c1, c0, cb) of a link from its coefficient word: CLI stores kappa =
+// (1 - 2q)/(1 + 2q), Bouzidi stores q, NaN marks a moving-wall link (simple
+// bounce-back plus the wall term).
+template <int BC>
+__device__ __forceinline__ void bb_coeffs(float prm, float& c1, float& c0, float& cb) {
+#pragma clang fp contract(off)
+    if (prm != prm) {
+        c1 = 1.0f; c0 = 0.0f; cb = 0.0f;
+    } else if (BC == LBM_BC_CLI) {
+        c1 = 1.0f; c0 = prm; cb = -prm;
+    } else if (BC == LBM_BC_BOUZIDI) {
+        if (prm < 0.5f) {
+            c1 = 2.0f * prm; c0 = 1.0f - 2.0f * prm; cb = 0.0f;
+        } else {
+            c1 = 1.0f / (2.0f * prm); c0 = 0.0f; cb = 1.0f - c1;
+        }
+    } else {
+        c1 = 1.0f; c0 = 0.0f; cb = 0.0f;
+    }
+}
+
+// TRT collision with Guo forcing split into even/odd parts, in place on g.
+__device__ __forceinline__ float collide(float (&g)[Q], const CellConsts& a) {
+    // no FP contraction: every kernel that inlines this evaluates the same
+    // sequence of roundings, so all of them agree bit for bit
+#pragma clang fp contract(off)
+    float drho = g[0];
+    float jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int k = 2 * p + 1;
+        const float s = g[k] + g[k + 1];
+        const float d = g[k] - g[k + 1];
+        drho += s;
+        if (L::ex[k]) jx += L::ex[k] * d;
+        if (L::ey[k]) jy += L::ey[k] * d;
+        if (L::ez[k]) jz += L::ez[k] * d;
+    }
+    const float ux = (jx + 0.5f * a.F[0]) * a.inv_rho0;
+    const float uy = (jy + 0.5f * a.F[1]) * a.inv_rho0;
+    const float uz = (jz + 0.5f * a.F[2]) * a.inv_rho0;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float uF = ux * a.F[0] + uy * a.F[1] + uz * a.F[2];
+    {
+        const float w0 = 1.0f / 3.0f;
+        const float eq = w0 * (drho - 1.5f * a.rho0 * uu);
+        g[0] = g[0] - a.wp * (g[0] - eq) + a.cp * (w0 * (-3.0f * uF));
+    }
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int k = 2 * p + 1;
+        const float w = (float)weight(k);
+        const float eu = L::ex[k] * ux + L::ey[k] * uy + L::ez[k] * uz;
+        const float eF = L::ex[k] * a.F[0] + L::ey[k] * a.F[1] + L::ez[k] * a.F[2];
+        const float eqp = w * (drho + a.rho0 * (4.5f * eu * eu - 1.5f * uu));
+        const float eqm = w * (3.0f * a.rho0 * eu);
+        const float gp = 0.5f * (g[k] + g[k + 1]);
+        const float gm = 0.5f * (g[k] - g[k + 1]);
+        const float sp = w * (9.0f * eu * eF - 3.0f * uF);
+        const float sm = w * (3.0f * eF);
+        const float dp = -a.wp * (gp - eqp) + a.cp * sp;
+        const float dm = -a.wm * (gm - eqm) + a.cm * sm;
+        const float gk = g[k], gkb = g[k + 1];
+        g[k] = gk + dp + dm;
+        g[k + 1] = gkb + dp - dm;
+    }
+    return ux;
+}
+
+typedef __attribute__((address_space(1))) float gfloat;
+
+template <bool NT>
+__device__ __forceinline__ float ld(const gfloat* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st(gfloat* p, float v) {
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// a pointer that is the same in every lane, kept in scalar registers
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// One cell of one time step: pull (with the partial bounce-back values),
+// link correction, collision, push and the next step's partial values.
+// Returns the x-velocity of this step's moments (0 for a solid cell).
+template <int LAYOUT, int PARITY, int BC, bool NT>
+__device__ __forceinline__ float cell_update(float* const* pa, float* const* pb, const uint32_t* __restrict__ info,
+                                             const int32_t* __restrict__ segbase,
+                                             const float* __restrict__ lparam, const CellConsts& K, int nx,
+                                             int ny, int nz, int c, int x, int y, int z) {
+#pragma clang fp contract(off)
+    const unsigned X[3] = {(unsigned)(x == 0 ? nx - 1 : x - 1), (unsigned)x, (unsigned)(x == nx - 1 ? 0 : x + 1)};
+    const unsigned Y[3] = {(unsigned)(y == 0 ? ny - 1 : y - 1), (unsigned)y, (unsigned)(y == ny - 1 ? 0 : y + 1)};
+    const unsigned Z[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1), (unsigned)z, (unsigned)(z == nz - 1 ? 0 : z + 1)};
+    const unsigned unx = (unsigned)nx, uny = (unsigned)ny;
+    const unsigned uc = (unsigned)c;
+    // linear index of x + (dx, dy, dz); all indices are below 2^31
+#define NB(dx, dy, dz) (X[(dx) + 1] + unx * (Y[(dy) + 1] + uny * Z[(dz) + 1]))
+
+    // Addressing: population k of cell i is at byte offset 4*i from the
+    // array base A + k*stride (uniform); 4*i fits 32 bits (the host limits a
+    // domain to 2^30 cells), so loads use a scalar base + 32-bit offset.
+#define AT(bases, k, idx) \
+    (*(__attribute__((address_space(1))) float*)((__attribute__((address_space(1))) char*)(bases)[k] + \
+                                                   ((uint32_t)(idx) << 2)))
+
+    // 1) streaming: the cell word and all 19 pulls are issued together; the
+    //    empty asm pins the pulls ahead of the solid-cell branch, so a
+    //    wavefront waits for memory once
+    const uint32_t inf = info[c];
+    float g[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        if (LAYOUT == L_TWOGRID)
+            g[k] = AT(pa, k, NB(-L::ex[k], -L::ey[k], -L::ez[k]));
+        else if (PARITY == P_EVEN)
+            g[k] = ld<NT>(&AT(pa, k, uc));
+        else
+            g[k] = AT(pa, opp(k), NB(-L::ex[k], -L::ey[k], -L::ez[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) asm volatile("" ::"v"(g[k]));
+    if (inf == CELL_SOLID_WORD) return 0.0f;
+    const uint32_t mask = inf & LINK_MASK_BITS;
+
+    // 2) links: the pulled value of an unknown population is the partial
+    //    value P stored last step; add c0 times the second node's value
+    if (mask) {
+        float prm[Q];
+        const int base = segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
+        // every coefficient load is issued before any is used, without
+        // branches: for a direction that is not a link the rank points at a
+        // neighbouring record (the array is padded), whose value is unused
+        const __attribute__((address_space(1))) char* lp = (const __attribute__((address_space(1))) char*)lparam;
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const int kk = opp(k);
+            const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
+            prm[k] = *(const __attribute__((address_space(1))) float*)(lp + (li << 2));
+        }
+        // in place: g[kk] is read only when (x, k) is not itself a link, so
+        // it still holds its pulled value
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const int kk = opp(k);
+            if (mask & (1u << (kk - 1))) {
+                float c1, c0, cb;
+                bb_coeffs<BC>(prm[k], c1, c0, cb);
+                if (c0 != 0.0f) g[k] += c0 * g[kk];
+            }
+        }
+    }
+
+    // 3) collision
+    const float ux = collide(g, K);
+
+    // 4) store
+    float* const* D = (LAYOUT == L_TWOGRID) ? pb : pa;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        if (LAYOUT == L_TWOGRID)
+            st<NT>(&AT(D, k, uc), g[k]);
+        else if (PARITY == P_EVEN)
+            st<NT>(&AT(D, opp(k), uc), g[k]);
+        else
+            AT(D, k, NB(L::ex[k], L::ey[k], L::ez[k])) = g[k];
+    }
+    // 5) partial bounce-back values for the next step; the coefficients are
+    //    read again (a cache hit) rather than held in registers across the
+    //    collision
+    if (mask) {
+        const int base = segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
+        const __attribute__((address_space(1))) char* lp = (const __attribute__((address_space(1))) char*)lparam;
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const int kk = opp(k);
+            if (mask & (1u << (kk - 1))) {
+                const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
+                const float pk = __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)(lp + (li << 2)));
+                float c1, c0, cb;
+                bb_coeffs<BC>(pk, c1, c0, cb);
+                const float P = c1 * g[kk] + cb * g[k] + (pk != pk ? K.wterm[k] : 0.0f);
+                if (LAYOUT == L_TWOGRID)
+                    AT(D, k, NB(L::ex[kk], L::ey[kk], L::ez[kk])) = P;
+                else if (PARITY == P_EVEN)
+                    AT(D, kk, NB(L::ex[kk], L::ey[kk], L::ez[kk])) = P;
+                else
+                    AT(D, k, uc) = P;
+            }
+        }
+    }
+    return ux;
+#undef NB
+}
+
+}  // namespace lbm

@@ -42,6 +42,15 @@ constexpr uint32_t LINK_MASK_BITS = 0x3FFFFu;
 enum Layout : int { L_TWOGRID = 0, L_AA = 1 };
 enum Parity : int { P_EVEN = 0, P_ODD = 1 };
 
+// collision constants shared by every cell of a run
+struct CellConsts {
+    float wp, wm;         // omega+, omega-
+    float cp, cm;         // 1 - omega+/2, 1 - omega-/2
+    float rho0, inv_rho0;
+    float F[3];
+    float wterm[Q];       // 6 w_k rho0 e_k.u_w for the moving wall
+};
+
 struct SweepArgs {
     float* A;        // populations (two-grid: source grid; AA: the only grid)
     float* B;        // two-grid destination grid (unused for AA)
@@ -53,14 +62,22 @@ struct SweepArgs {
     const float* lparam;  // CLI: kappa; Bouzidi: q; NaN: moving-wall bounce-back;
                           // padded with Q entries so that rank lookups stay in bounds
     int32_t nx, ny, nz, ncells;
-    float wp, wm;         // omega+, omega-
-    float cp, cm;         // 1 - omega+/2, 1 - omega-/2
-    float rho0, inv_rho0;
-    float F[3];
-    float wterm[Q];       // 6 w_k rho0 e_k.u_w for the moving wall
+    CellConsts k;
     int32_t xcd_remap;
     int32_t nt;           // non-temporal hints on the aligned streams
 };
+
+struct DeviceImages {
+    std::vector<uint32_t> info;
+    std::vector<int32_t> segbase;
+    std::vector<float> lparam;
+    std::vector<int64_t> seed_idx;
+    std::vector<float> seed_val;
+};
+lbm_status build_images(const DomainGeo& G, int layout, int64_t stride, const CellConsts& K, DeviceImages& im,
+                        std::string& err);
+
+CellConsts make_consts(const lbm_params& p, double wp, double wm, const double* wall_velocity);
 
 hipError_t launch_sweep(const SweepArgs& a, int layout, int parity, int bc, int block, hipStream_t s);
 

@@ -182,6 +182,14 @@ class Context:
         check(lib.lbm_get_launch(self.ptr, C.byref(b), C.byref(r)), "lbm_get_launch")
         return b.value, r.value
 
+    def batch_set_launch(self, block, workgroups_per_domain):
+        check(lib.lbm_batch_set_launch(self.ptr, block, workgroups_per_domain), "lbm_batch_set_launch")
+
+    def batch_get_launch(self):
+        b, w = C.c_int32(), C.c_int32()
+        check(lib.lbm_batch_get_launch(self.ptr, C.byref(b), C.byref(w)), "lbm_batch_get_launch")
+        return b.value, w.value
+
     def autotune(self, steps_per_trial=20):
         check(lib.lbm_autotune(self.ptr, steps_per_trial), "lbm_autotune")
-        return self.get_launch() if len(self.domains) == 1 else None
+        return self.get_launch() if len(self.domains) == 1 else self.batch_get_launch()

@@ -1,0 +1,132 @@
+"""Batched persistent launch (many REV samples in one cooperative kernel).
+
+Every domain of a batch must evolve exactly as the same domain stepped alone
+by the single-domain sweep (same cell arithmetic), for every launch shape;
+run-to-steady must agree with the FP64 oracle's steady permeability.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1507_06565_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _lbm():
+    from paper_1507_06565_amd import lbm
+    return lbm
+
+
+def small_rev(i, edge, seed0=500):
+    """Small periodic REV cube with a few spheres (seeded)."""
+    rng = np.random.default_rng(seed0 + i)
+    n = 3 + i % 3
+    S = W.quantise(np.column_stack([rng.uniform(0, edge, n), rng.uniform(0, edge, n), rng.uniform(0, edge, n),
+                                    rng.uniform(2.0, edge / 4.0, n)]))
+    return W.Domain(edge, edge, edge, periodic=(1, 1, 1), wall_lo=(0, 0, 0), wall_hi=(0, 0, 0), spheres=S, bc="cli")
+
+
+def batch_domains():
+    edges = [16, 24, 20, 32, 12, 28, 16]
+    return [small_rev(i, e) for i, e in enumerate(edges)]
+
+
+PARAMS = W.Params(collision="trt", tau_plus=1.0, magic_lambda=3 / 16, force=(1e-5, 0.0, 0.0), layout="aa")
+
+
+def test_batch_equals_single_domain_runs_bitwise():
+    say("test_batch_equals_single_domain_runs_bitwise")
+    lbm = _lbm()
+    doms = batch_domains()
+    ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+    ctx.step(37)
+    ctx.step(20)
+    for i, d in enumerate(doms):
+        single = lbm.Context(lbm.Geometry(d), PARAMS)
+        single.step(57)
+        _, u1 = single.fields()
+        _, u2 = ctx.fields(i)
+        assert np.array_equal(u1, u2), i
+
+
+def test_batch_launch_shapes_bitwise():
+    say("test_batch_launch_shapes_bitwise")
+    lbm = _lbm()
+    doms = batch_domains()
+    base = None
+    for block, w in [(256, 1), (512, 2), (1024, 4), (256, 3), (512, 16)]:
+        ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+        ctx.batch_set_launch(block, w)
+        steps = ctx.run_to_steady(rel_tol=1e-6, check_every=50, max_steps=3000)
+        us = [ctx.fields(i)[1] for i in range(len(doms))]
+        if base is None:
+            base = (steps, us)
+        assert np.array_equal(steps, base[0]), (block, w)
+        for a, b in zip(us, base[1]):
+            assert np.array_equal(a, b), (block, w)
+
+
+def test_batch_fixed_steps_parity_with_oracle():
+    say("test_batch_fixed_steps_parity_with_oracle")
+    lbm = _lbm()
+    doms = batch_domains()[:4]
+    ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+    ctx.step(150)
+    for i, d in enumerate(doms):
+        ref = oracle.Sim(d, PARAMS)
+        ref.step(150)
+        _, u = ctx.fields(i)
+        fl = np.broadcast_to(ref.fluid(), u.shape)
+        e = np.linalg.norm((u - ref.velocity())[fl]) / np.linalg.norm(ref.velocity()[fl])
+        say("domain", i, "rel L2", e)
+        assert e <= 1e-4
+
+
+def test_batch_run_to_steady_permeability():
+    """Steady-state test (relative change of the mean velocity over
+    check_every steps) and Darcy permeability (eq. (1)) per sample against
+    the oracle run to its own steady state."""
+    say("test_batch_run_to_steady_permeability")
+    lbm = _lbm()
+    doms = [small_rev(0, 16), small_rev(1, 20), small_rev(2, 12)]
+    ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+    steps = ctx.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=200000)
+    say("steps", steps)
+    assert np.all(steps < 200000)
+    for i, d in enumerate(doms):
+        k = ctx.permeability(i, 0)
+        ref = oracle.Sim(d, PARAMS)
+        prev = None
+        for _ in range(2000):
+            ref.step(100)
+            U = ref.velocity()[0][ref.fluid()].sum()
+            if prev is not None and abs(U - prev) <= 1e-10 * abs(U):
+                break
+            prev = U
+        sup, _, _ = oracle.plane_profile(ref.velocity(), ref.fluid(), 2, 0)
+        kref = oracle.permeability(sup, 0, d.nz, 1.0 / 6.0, 1.0, 1e-5)
+        say("domain", i, "K", k, "oracle", kref)
+        assert abs(k / kref - 1) <= 2e-4
+
+
+def test_batch_restart_bitwise():
+    say("test_batch_restart_bitwise")
+    lbm = _lbm()
+    doms = batch_domains()[:3]
+    g = lbm.Geometry(doms)
+    a = lbm.Context(g, PARAMS)
+    a.step(21)
+    img = a.save()
+    a.step(10)
+    b = lbm.Context(g, PARAMS)
+    b.load(img)
+    b.step(10)
+    for i in range(3):
+        assert np.array_equal(a.fields(i)[1], b.fields(i)[1])
