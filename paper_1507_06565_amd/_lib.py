@@ -64,6 +64,15 @@ _sig = {
     "lbm_batch_set_launch": ([vp, i32, i32], i32),
     "lbm_batch_get_launch": ([vp, P(i32), P(i32)], i32),
     "lbm_destroy": ([vp], None),
+    # gray columns (include/gray.h)
+    "gray_required_bytes": ([i32, i32, P(i64)], i32),
+    "gray_init": ([i32, i32, i32, vp, vp, vp, f64, f64, vp, vp, vp, i64, vp, P(vp)], i32),
+    "gray_set_cells": ([vp, vp, vp, vp], i32),
+    "gray_reset": ([vp], i32),
+    "gray_run": ([vp, i64], i32),
+    "gray_run_to_steady": ([vp, f64, i64, i64, vp], i32),
+    "gray_profile": ([vp, i32, vp], i32),
+    "gray_destroy": ([vp], None),
 }
 
 EXPORTS = []

@@ -28,7 +28,4 @@ lbm_status batch_set_launch(BatchCtx* b, int32_t block, int32_t W);
 lbm_status batch_get_launch(BatchCtx* b, int32_t* block, int32_t* W);
 void batch_destroy(BatchCtx* b);
 
-// error text for the calling thread (defined with the C ABI)
-lbm_status set_error(lbm_status s, const std::string& msg);
-
 }  // namespace lbm

@@ -1,0 +1,367 @@
+// Gray (homogenised) lattice Boltzmann model for flow in and over a porous
+// medium: the generalised Navier-Stokes model of Sec. 4, eqs.
+// (GeneralizedPor1), (GeneralizedPor2), (PorousForce), discretised as in the
+// cited Guo & Zhao (2002) model, in its incompressible variant with shifted
+// populations and a TRT collision, Forchheimer coefficient zero (Stokes
+// regime, Sec. 4).
+//
+// A column is 1 x 1 x nz cells, periodic in x and y, so every population
+// streams along z only.  Per cell: porosity eps, effective viscosity nu_eff
+// (tau+ = 3 nu_eff + 1/2; omega- from the magic parameter) and the Darcy drag
+// coefficient D = eps nu / K (0 in free fluid):
+//   v      = sum_k e_k g_k / rho0 + eps G / 2
+//   u      = v / (1 + D / 2)                     (implicit drag, c_F = 0)
+//   F      = -D u + eps G                        (eq. (PorousForce))
+//   g_eq_k = w_k [drho + rho0 (3 e.u + 4.5 (e.u)^2 / eps - 1.5 u.u / eps)]
+//   S_k    = w_k rho0 [3 e.F + 9 (e.u)(e.F) / eps - 3 u.F / eps]
+// with S split into even and odd parts relaxed by (1 - omega+/2) and
+// (1 - omega-/2).  Optional wall layers at z = 0 and z = nz-1 (half-way
+// bounce-back; the top wall may move, Ladd's correction).
+//
+// One workgroup per column, one thread per cell, the whole state resident in
+// LDS (19 * nz floats, 38 KB for nz = 512), the time loop inside the kernel;
+// global memory is touched only to load and store the state and to write the
+// final profile.  The steady-state test (relative change of the FP64 sum of
+// u_x over check_every steps) is evaluated in the kernel with a fixed-order
+// workgroup reduction.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gray.h"
+#include "internal.hpp"
+
+namespace lbm {
+
+struct GrayArgs {
+    float* state;         // ncols x 19 x nz
+    const float* cell;    // ncols x nz x 4: eps, omega+, omega-, D
+    double* u;            // ncols x nz x 3
+    int64_t* steps;       // per column
+    double* uprev;        // per column
+    int32_t* status;      // per column: 0 running, 1 converged, -1 unstable
+    int32_t nz, walls, steady, check_every;
+    int64_t nsteps;
+    double tol;
+    float rho0, G[3];
+    float wterm[Q];
+};
+
+namespace {
+
+using L = D3Q19;
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
+#pragma clang fp contract(off)
+    extern __shared__ float lds[];  // Q * nz populations
+    __shared__ double red[BLOCK];
+    __shared__ int s_stop;
+    const int col = blockIdx.x;
+    const int z = threadIdx.x;
+    const int nz = a.nz;
+    const bool live = z < nz;
+    const bool solid = a.walls && (z == 0 || z == nz - 1);
+    float* gs = a.state + (int64_t)col * Q * nz;
+    float eps = 1.0f, wp = 1.0f, wm = 1.0f, D = 0.0f;
+    if (live) {
+        const float* cp = a.cell + ((int64_t)col * nz + z) * 4;
+        eps = cp[0]; wp = cp[1]; wm = cp[2]; D = cp[3];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) lds[k * nz + z] = gs[k * nz + z];
+    }
+    const float inv_eps = 1.0f / eps;
+    const float cpl = 1.0f - 0.5f * wp, cmi = 1.0f - 0.5f * wm;
+    const float Ge[3] = {eps * a.G[0], eps * a.G[1], eps * a.G[2]};
+    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+    const int64_t s0 = a.steps[col];
+    int64_t s = s0;
+    bool stop = a.nsteps <= 0 || (a.steady && a.status[col] != 0);
+    while (!stop) {
+        __syncthreads();
+        float g[Q];
+        if (live && !solid) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                int zs = z - L::ez[k];
+                if (a.walls && (zs == 0 || zs == nz - 1)) {
+                    // half-way bounce-back from a wall layer
+                    g[k] = lds[opp(k) * nz + z] + (zs == nz - 1 ? a.wterm[k] : 0.0f);
+                } else {
+                    zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
+                    g[k] = lds[k * nz + zs];
+                }
+            }
+        }
+        __syncthreads();
+        if (live && !solid) {
+            float drho = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+            for (int p = 0; p < 9; ++p) {
+                const int k = 2 * p + 1;
+                const float sm = g[k] + g[k + 1], df = g[k] - g[k + 1];
+                drho += sm;
+                if (L::ex[k]) jx += L::ex[k] * df;
+                if (L::ey[k]) jy += L::ey[k] * df;
+                if (L::ez[k]) jz += L::ez[k] * df;
+            }
+            const float r = 1.0f / a.rho0;
+            const float den = 1.0f / (1.0f + 0.5f * D);
+            ux = (jx * r + 0.5f * Ge[0]) * den;
+            uy = (jy * r + 0.5f * Ge[1]) * den;
+            uz = (jz * r + 0.5f * Ge[2]) * den;
+            const float Fx = -D * ux + Ge[0], Fy = -D * uy + Ge[1], Fz = -D * uz + Ge[2];
+            const float uu = ux * ux + uy * uy + uz * uz;
+            const float uF = ux * Fx + uy * Fy + uz * Fz;
+            {
+                const float w0 = 1.0f / 3.0f;
+                const float eq = w0 * (drho - 1.5f * a.rho0 * uu * inv_eps);
+                const float src = w0 * a.rho0 * (-3.0f * uF * inv_eps);
+                lds[z] = g[0] - wp * (g[0] - eq) + cpl * src;
+            }
+#pragma unroll
+            for (int p = 0; p < 9; ++p) {
+                const int k = 2 * p + 1;
+                const float w = (float)weight(k);
+                const float eu = L::ex[k] * ux + L::ey[k] * uy + L::ez[k] * uz;
+                const float eF = L::ex[k] * Fx + L::ey[k] * Fy + L::ez[k] * Fz;
+                const float eqp = w * (drho + a.rho0 * (4.5f * eu * eu * inv_eps - 1.5f * uu * inv_eps));
+                const float eqm = w * (3.0f * a.rho0 * eu);
+                const float sp = w * a.rho0 * (9.0f * eu * eF * inv_eps - 3.0f * uF * inv_eps);
+                const float smn = w * a.rho0 * (3.0f * eF);
+                const float gp = 0.5f * (g[k] + g[k + 1]);
+                const float gm = 0.5f * (g[k] - g[k + 1]);
+                const float dp = -wp * (gp - eqp) + cpl * sp;
+                const float dm = -wm * (gm - eqm) + cmi * smn;
+                lds[k * nz + z] = g[k] + dp + dm;
+                lds[(k + 1) * nz + z] = g[k + 1] + dp - dm;
+            }
+        } else if (live) {
+            ux = uy = uz = 0.0f;
+        }
+        ++s;
+        stop = s - s0 >= a.nsteps;
+        if (a.steady && ((s - s0) % a.check_every == 0)) {
+            red[threadIdx.x] = (live && !solid) ? (double)ux : 0.0;
+            __syncthreads();
+            for (int w = BLOCK / 2; w > 0; w >>= 1) {
+                if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const double U = red[0], Up = a.uprev[col];
+                int st = 0;
+                if (!(fabs(U) < 0.4 * nz)) st = -1;
+                else if (fabs(U - Up) <= a.tol * fabs(U)) st = 1;
+                a.uprev[col] = U;
+                if (st != 0) a.status[col] = st;
+                s_stop = st;
+            }
+            __syncthreads();
+            if (s_stop != 0) stop = true;
+        }
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) gs[k * nz + z] = lds[k * nz + z];
+        double* uo = a.u + ((int64_t)col * nz + z) * 3;
+        uo[0] = ux; uo[1] = uy; uo[2] = uz;
+    }
+    if (threadIdx.x == 0) a.steps[col] = s;
+}
+
+int64_t align_up(int64_t v, int64_t al) { return (v + al - 1) / al * al; }
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+struct gray_ctx {
+    int ncols = 0, nz = 0, walls = 0;
+    hipStream_t stream = nullptr;
+    char* buf = nullptr;
+    int64_t off_state = 0, off_cell = 0, off_u = 0, off_steps = 0, off_uprev = 0, off_status = 0;
+    GrayArgs args{};
+    double lambda = 3.0 / 16.0, rho0 = 1.0;
+    std::vector<int64_t> steps;
+};
+
+namespace {
+
+struct GPlan {
+    int64_t state, cell, u, steps, uprev, status, total;
+};
+
+GPlan gplan(int ncols, int nz) {
+    GPlan P{};
+    int64_t o = 0;
+    P.state = o; o = align_up(o + (int64_t)ncols * Q * nz * 4, 256);
+    P.cell = o; o = align_up(o + (int64_t)ncols * nz * 16, 256);
+    P.u = o; o = align_up(o + (int64_t)ncols * nz * 24, 256);
+    P.steps = o; o = align_up(o + (int64_t)ncols * 8, 256);
+    P.uprev = o; o = align_up(o + (int64_t)ncols * 8, 256);
+    P.status = o; o = align_up(o + (int64_t)ncols * 4, 256);
+    P.total = o;
+    return P;
+}
+
+#define GCHK(expr, what)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return set_error(LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+lbm_status upload_cells(gray_ctx* c, const double* eps, const double* nu_eff, const double* drag) {
+    const int64_t n = (int64_t)c->ncols * c->nz;
+    std::vector<float> cell((size_t)n * 4);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(eps[i] > 0.0 && eps[i] <= 1.0)) return set_error(LBM_E_INVAL, "porosity must lie in (0, 1]");
+        if (!(nu_eff[i] > 0.0) || !std::isfinite(nu_eff[i])) return set_error(LBM_E_INVAL, "nu_eff must be positive");
+        if (!(drag[i] >= 0.0) || !std::isfinite(drag[i])) return set_error(LBM_E_INVAL, "drag must be >= 0");
+        const double tp = 3.0 * nu_eff[i] + 0.5;
+        const double tm = 0.5 + c->lambda / (tp - 0.5);
+        const double wp = 1.0 / tp, wm = 1.0 / tm;
+        if (!(wm > 0.0 && wm < 2.0)) return set_error(LBM_E_INVAL, "omega- outside (0, 2)");
+        cell[4 * i + 0] = (float)eps[i];
+        cell[4 * i + 1] = (float)wp;
+        cell[4 * i + 2] = (float)wm;
+        cell[4 * i + 3] = (float)drag[i];
+    }
+    GCHK(hipMemcpyAsync(c->buf + c->off_cell, cell.data(), cell.size() * 4, hipMemcpyHostToDevice, c->stream),
+         "upload cell parameters");
+    GCHK(hipStreamSynchronize(c->stream), "synchronise");
+    return LBM_OK;
+}
+
+lbm_status launch(gray_ctx* c) {
+    const int block = (int)align_up(c->nz, 64);
+    const size_t lds = (size_t)Q * c->nz * 4;
+    hipError_t e;
+    switch (block) {
+#define GB(B) case B: k_gray<B><<<c->ncols, B, lds, c->stream>>>(c->args); break;
+        GB(64) GB(128) GB(192) GB(256) GB(320) GB(384) GB(448) GB(512) GB(576) GB(640) GB(704)
+#undef GB
+        default: return set_error(LBM_E_INVAL, "column height must be at most 704");
+    }
+    e = hipGetLastError();
+    GCHK(e, "gray launch");
+    c->steps.assign(c->ncols, 0);
+    GCHK(hipMemcpyAsync(c->steps.data(), c->buf + c->off_steps, c->ncols * 8, hipMemcpyDeviceToHost, c->stream),
+         "read steps");
+    GCHK(hipStreamSynchronize(c->stream), "synchronise");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status gray_required_bytes(int32_t ncols, int32_t nz, int64_t* bytes) {
+    // the column (19 * nz floats) and the reduction buffer must fit the 64 KB
+    // of LDS a workgroup gets without opting in to more
+    if (ncols < 1 || nz < 3 || nz > 704 || !bytes) return set_error(LBM_E_INVAL, "need ncols >= 1 and 3 <= nz <= 704");
+    *bytes = gplan(ncols, nz).total;
+    return LBM_OK;
+}
+
+lbm_status gray_init(int32_t ncols, int32_t nz, int32_t walls, const double* eps, const double* nu_eff,
+                     const double* drag, double magic_lambda, double rho0, const double* G, const double* lid,
+                     void* dev_buf, int64_t bytes, void* hip_stream, gray_ctx** out) {
+    if (!out || !eps || !nu_eff || !drag || !G || !dev_buf) return set_error(LBM_E_INVAL, "bad arguments");
+    *out = nullptr;
+    int64_t need = 0;
+    lbm_status s = gray_required_bytes(ncols, nz, &need);
+    if (s != LBM_OK) return s;
+    if (bytes < need) return set_error(LBM_E_NOMEM, "device buffer smaller than gray_required_bytes");
+    if (!(rho0 > 0.0) || !(magic_lambda > 0.0)) return set_error(LBM_E_INVAL, "rho0 and Lambda must be positive");
+    auto* c = new gray_ctx;
+    c->ncols = ncols; c->nz = nz; c->walls = walls ? 1 : 0;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->buf = reinterpret_cast<char*>(dev_buf);
+    c->lambda = magic_lambda; c->rho0 = rho0;
+    const GPlan P = gplan(ncols, nz);
+    c->off_state = P.state; c->off_cell = P.cell; c->off_u = P.u; c->off_steps = P.steps; c->off_uprev = P.uprev;
+    c->off_status = P.status;
+    GrayArgs& a = c->args;
+    a.state = reinterpret_cast<float*>(c->buf + P.state);
+    a.cell = reinterpret_cast<const float*>(c->buf + P.cell);
+    a.u = reinterpret_cast<double*>(c->buf + P.u);
+    a.steps = reinterpret_cast<int64_t*>(c->buf + P.steps);
+    a.uprev = reinterpret_cast<double*>(c->buf + P.uprev);
+    a.status = reinterpret_cast<int32_t*>(c->buf + P.status);
+    a.nz = nz; a.walls = c->walls;
+    a.rho0 = (float)rho0;
+    for (int i = 0; i < 3; ++i) a.G[i] = (float)G[i];
+    const double zero[3] = {0, 0, 0};
+    const double* lw = lid ? lid : zero;
+    for (int k = 0; k < Q; ++k)
+        a.wterm[k] = (float)(6.0 * weight(k) * rho0 * (D3Q19::ex[k] * lw[0] + D3Q19::ey[k] * lw[1] + D3Q19::ez[k] * lw[2]));
+    s = upload_cells(c, eps, nu_eff, drag);
+    if (s == LBM_OK) s = gray_reset(c);
+    if (s != LBM_OK) { delete c; return s; }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status gray_reset(gray_ctx* c) {
+    if (!c) return set_error(LBM_E_INVAL, "null context");
+    std::vector<double> nanv(c->ncols, NAN);
+    GCHK(hipMemsetAsync(c->buf + c->off_state, 0, (size_t)c->ncols * Q * c->nz * 4, c->stream), "zero state");
+    GCHK(hipMemsetAsync(c->buf + c->off_u, 0, (size_t)c->ncols * c->nz * 24, c->stream), "zero profile");
+    GCHK(hipMemsetAsync(c->buf + c->off_steps, 0, (size_t)c->ncols * 8, c->stream), "zero steps");
+    GCHK(hipMemsetAsync(c->buf + c->off_status, 0, (size_t)c->ncols * 4, c->stream), "zero status");
+    GCHK(hipMemcpyAsync(c->buf + c->off_uprev, nanv.data(), c->ncols * 8, hipMemcpyHostToDevice, c->stream), "history");
+    GCHK(hipStreamSynchronize(c->stream), "synchronise");
+    c->steps.assign(c->ncols, 0);
+    return LBM_OK;
+}
+
+lbm_status gray_set_cells(gray_ctx* c, const double* eps, const double* nu_eff, const double* drag) {
+    if (!c || !eps || !nu_eff || !drag) return set_error(LBM_E_INVAL, "bad arguments");
+    return upload_cells(c, eps, nu_eff, drag);
+}
+
+lbm_status gray_run(gray_ctx* c, int64_t nsteps) {
+    if (!c || nsteps < 0) return set_error(LBM_E_INVAL, "bad arguments");
+    c->args.steady = 0;
+    c->args.nsteps = nsteps;
+    c->args.check_every = 1;
+    c->args.tol = 0.0;
+    return launch(c);
+}
+
+lbm_status gray_run_to_steady(gray_ctx* c, double rel_tol, int64_t check_every, int64_t max_steps,
+                              int64_t* steps_done) {
+    if (!c || !(rel_tol >= 0.0) || check_every < 1 || check_every > (1 << 30) || max_steps < 0)
+        return set_error(LBM_E_INVAL, "bad arguments");
+    c->args.steady = 1;
+    c->args.nsteps = max_steps;
+    c->args.check_every = (int32_t)check_every;
+    c->args.tol = rel_tol;
+    lbm_status s = launch(c);
+    if (s != LBM_OK) return s;
+    if (steps_done) std::memcpy(steps_done, c->steps.data(), c->ncols * 8);
+    std::vector<int32_t> st(c->ncols);
+    GCHK(hipMemcpyAsync(st.data(), c->buf + c->off_status, c->ncols * 4, hipMemcpyDeviceToHost, c->stream), "status");
+    GCHK(hipStreamSynchronize(c->stream), "synchronise");
+    for (int i = 0; i < c->ncols; ++i)
+        if (st[i] < 0) return set_error(LBM_E_UNSTABLE, "gray column " + std::to_string(i) + " became unstable");
+    return LBM_OK;
+}
+
+lbm_status gray_profile(gray_ctx* c, int32_t col, double* u) {
+    if (!c || !u || col < 0 || col >= c->ncols) return set_error(LBM_E_INVAL, "bad arguments");
+    GCHK(hipMemcpyAsync(u, c->buf + c->off_u + (int64_t)col * c->nz * 24, (size_t)c->nz * 24, hipMemcpyDeviceToHost,
+                        c->stream), "copy profile");
+    GCHK(hipStreamSynchronize(c->stream), "synchronise");
+    return LBM_OK;
+}
+
+void gray_destroy(gray_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -27,6 +27,9 @@ struct DomainGeo {
 
 lbm_status build_domain(const lbm_domain_desc& d, DomainGeo& out, std::string& err);
 
+// error text for the calling thread (defined with the C ABI); returns s
+lbm_status set_error(lbm_status s, const std::string& msg);
+
 // ----------------------------------------------------------- device layout --
 // One 32-bit word per cell:
 //   CELL_SOLID_WORD (all ones)  solid cell, not updated;

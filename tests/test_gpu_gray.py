@@ -1,0 +1,84 @@
+"""Gray (homogenised) column kernel against the FP64 oracle, through the C ABI."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+NU = 1.0 / 6.0
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _gray():
+    from paper_1507_06565_amd import gray
+    return gray
+
+
+def smoothed_step(nz, seed):
+    from paper_1507_06565_amd import workloads as W
+    eps, _, _ = W.smoothed_step_porosity(nz, seed)
+    return eps
+
+
+def test_fixed_steps_parity_with_oracle():
+    """Several columns with different porosity profiles (smoothed steps),
+    Lundgren viscosity nu/eps and a Kozeny-Carman drag, 3000 steps."""
+    say("test_fixed_steps_parity_with_oracle")
+    gray = _gray()
+    nz, ncols = 130, 4
+    eps = np.stack([smoothed_step(nz, j) for j in range(ncols)])
+    nue = NU / eps
+    K = 2.0 * eps ** 3 / (1 - eps + 1e-12) ** 2
+    drag = np.where(eps < 1.0, eps * NU / K, 0.0)
+    g = gray.GrayColumns(eps, nue, drag, G=(1e-6, 0, 0), walls=True)
+    g.run(3000)
+    for j in range(ncols):
+        ref, _ = oracle.gray_run(nz, eps[j], nue[j], drag[j], G=(1e-6, 0, 0), walls=True, nsteps=3000)
+        got = g.profile(j)
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        say("column", j, "rel L2", e)
+        assert e <= 1e-4
+
+
+def test_steady_brinkman_and_couette():
+    say("test_steady_brinkman_and_couette")
+    gray = _gray()
+    # Brinkman channel
+    H = 64
+    nz, eps, nue, G = H + 2, 0.6, 2 * NU, 1e-6
+    K = (H / 10) ** 2 * eps * NU / nue
+    g = gray.GrayColumns(np.full(nz, eps), np.full(nz, nue), np.full(nz, eps * NU / K), G=(G, 0, 0), walls=True)
+    steps = g.run_to_steady(1e-9, 500, 500000)
+    u = g.profile(0)[:, 0]
+    r = math.sqrt(eps * NU / (nue * K))
+    s = np.arange(nz) - 0.5
+    exact = K * G / NU * (1 - np.cosh(r * (s - H / 2)) / np.cosh(r * H / 2))
+    err = np.max(np.abs(u[1:-1] - exact[1:-1])) / np.max(exact)
+    say("brinkman steps", steps, "err", err)
+    assert err < 1e-3
+    # two-layer Couette (Sec. 4), Re = 0.1, Da = 1.2e-4
+    u0, Da, epsp, J = 0.1 * NU / H, 1.2e-4, 0.5, 2.0
+    Kc = Da * H * H
+    y = np.arange(nz) - 0.5
+    por = y < H / 2
+    e_, n_, d_ = np.where(por, epsp, 1.0), np.where(por, J * NU, NU), np.where(por, epsp * NU / Kc, 0.0)
+    g = gray.GrayColumns(e_, n_, d_, G=(0, 0, 0), walls=True, lid=(u0, 0, 0))
+    g.run_to_steady(1e-10, 1000, 2_000_000)
+    ref, _ = oracle.gray_to_steady(nz, e_, n_, d_, lid=(u0, 0, 0), walls=True, rel_tol=1e-13, check=1000)
+    u = g.profile(0)[:, 0]
+    assert np.max(np.abs(u - ref[:, 0])) <= 1e-4 * u0
+
+
+def test_darcy_limit_periodic():
+    gray = _gray()
+    nz, eps, K, G = 16, 0.5, 3.0, 1e-6
+    g = gray.GrayColumns(np.full(nz, eps), np.full(nz, NU), np.full(nz, eps * NU / K), G=(G, 0, 0), walls=False)
+    g.run_to_steady(1e-12, 200, 200000)
+    u = g.profile(0)[:, 0]
+    assert np.max(np.abs(u / (K * G / NU) - 1)) < 1e-5

@@ -1,0 +1,97 @@
+"""Pins of the oracle's gray (homogenised, Sec. 4) column model.
+
+Checked against closed forms of the continuum model it discretises
+(eqs. (GeneralizedPor2), (PorousForce), (SteadyVelocity)): the Darcy limit,
+the free-fluid limit (the pore-scale scheme's Poiseuille closed form), the
+Brinkman channel and the two-layer Couette flow of Sec. 4, with second-order
+convergence in the grid spacing.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+NU = 1.0 / 6.0
+
+
+def steady(nz, eps, nue, drag, **kw):
+    u, steps = oracle.gray_to_steady(nz, eps, nue, drag, rel_tol=1e-13, check=500, max_steps=2_000_000, **kw)
+    return u[:, 0]
+
+
+@pytest.mark.parametrize("eps,K", [(0.5, 3.0), (0.9, 40.0), (0.35, 0.2)])
+def test_darcy_limit_exact(eps, K):
+    """Uniform porosity and permeability, periodic column: the steady state is
+    Darcy's law u = K G / nu exactly (eq. (1), the drag balancing eps G)."""
+    nz, G = 12, 1e-6
+    u = steady(nz, np.full(nz, eps), np.full(nz, NU), np.full(nz, eps * NU / K), G=(G, 0, 0), walls=False)
+    assert np.max(np.abs(u - K * G / NU)) <= 1e-10 * K * G / NU
+
+
+@pytest.mark.parametrize("lam", [3 / 16, 0.25])
+def test_free_fluid_limit_is_the_pore_scale_scheme(lam):
+    """eps = 1, no drag: the model is the pore-scale scheme, whose bounce-back
+    Poiseuille steady state is u = G s (H - s)/(2 nu) + G (16 Lambda - 3)/(24 nu)."""
+    nz, G, nue = 32, 1e-6, 0.1
+    u = steady(nz, np.ones(nz), np.full(nz, nue), np.zeros(nz), G=(G, 0, 0), walls=True, magic_lambda=lam)
+    s = np.arange(nz) - 0.5
+    H = nz - 2
+    exact = G / (2 * nue) * s * (H - s) + G * (16 * lam - 3) / (24 * nue)
+    assert np.max(np.abs(u[1:-1] - exact[1:-1])) <= 1e-10 * np.max(exact)
+
+
+def test_brinkman_channel_second_order():
+    """Uniform porous channel between walls: nu_eff u'' - (eps nu/K) u + eps G = 0,
+    u = (K G/nu)(1 - cosh(r (s - H/2))/cosh(r H/2)), r = sqrt(eps nu/(nu_eff K))."""
+    errs = []
+    for H in (32, 64):
+        nz, eps, nue, G = H + 2, 0.6, 2 * NU, 1e-6
+        K = (H / 10) ** 2 * eps * NU / nue
+        u = steady(nz, np.full(nz, eps), np.full(nz, nue), np.full(nz, eps * NU / K), G=(G, 0, 0), walls=True)
+        r = math.sqrt(eps * NU / (nue * K))
+        s = np.arange(nz) - 0.5
+        exact = K * G / NU * (1 - np.cosh(r * (s - H / 2)) / np.cosh(r * H / 2))
+        errs.append(np.max(np.abs(u[1:-1] - exact[1:-1])) / np.max(exact))
+    assert errs[1] < 1e-3
+    assert errs[0] / errs[1] > 3.5  # second order
+
+
+def couette_exact(H, u0, epsp, J, K):
+    """Two-layer Couette flow (Sec. 4): porous lower half (eps, nu_eff = J nu,
+    drag eps nu/K), free upper half, lid u0.  Exact Stokes solution:
+    u = A sinh(r y) below H/2, u = A sinh(r H/2) + C (y - H/2) above, with
+    continuity of u and of the shear stress (J nu A r cosh(r H/2) = nu C)."""
+    r = math.sqrt(epsp / (J * K))
+    h = H / 2
+    A = u0 / (math.sinh(r * h) + J * r * math.cosh(r * h) * h)
+    C = J * A * r * math.cosh(r * h)
+    return r, A, C
+
+
+@pytest.mark.parametrize("J", [1.0, 2.0])
+def test_couette_two_layer_second_order(J):
+    """Re = u0 H/nu = 0.1 and Da = K/H^2 = 1.2e-4 as in Sec. 4; the exact form
+    also agrees with the paper's exponential approximation (r H/2 >> 1)."""
+    errs = []
+    for H in (32, 64):
+        nz, u0, Da, epsp = H + 2, 0.1 * NU / H, 1.2e-4, 0.5
+        K = Da * H * H
+        y = np.arange(nz) - 0.5
+        por = y < H / 2
+        u = steady(nz, np.where(por, epsp, 1.0), np.where(por, J * NU, NU), np.where(por, epsp * NU / K, 0.0),
+                   G=(0, 0, 0), walls=True, lid=(u0, 0, 0))
+        r, A, C = couette_exact(H, u0, epsp, J, K)
+        h = H / 2
+        exact = np.where(y <= h, A * np.sinh(r * np.clip(y, 0, None)), A * math.sinh(r * h) + C * (y - h))
+        a = 2 * u0 / (2 * r * K + epsp * H)
+        paper = np.where(y >= h, r * K * a + epsp * a * (y - h), r * K * a * np.exp(r * (y - h)))
+        # the paper's form is the r H/2 >> 1 limit of the exact one (its r
+        # carries nu_eff, so it holds for every viscosity ratio J)
+        assert np.max(np.abs(paper[1:-1] - exact[1:-1])) <= 1e-6 * u0
+        errs.append(np.max(np.abs(u[1:-1] - exact[1:-1])) / u0)
+    # the porous boundary layer is 1/r = 1 (J = 1) to 1.4 (J = 2) cells thick
+    # at H = 64, hence the looser bound; the order is what is pinned
+    assert errs[1] < 3e-3
+    assert errs[0] / errs[1] > 3.5
