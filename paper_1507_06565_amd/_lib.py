@@ -73,6 +73,15 @@ _sig = {
     "gray_run_to_steady": ([vp, f64, i64, i64, vp], i32),
     "gray_profile": ([vp, i32, vp], i32),
     "gray_destroy": ([vp], None),
+    # closure network (include/mlp.h)
+    "mlp_workspace_bytes": ([i64, P(i64)], i32),
+    "mlp_pack_bf16": ([vp, vp, vp], i32),
+    "mlp_forward": ([vp, vp, vp, i64, vp, vp, vp], i32),
+    "mlp_backward": ([vp, vp, vp, vp, vp, i64, vp, vp, vp], i32),
+    "mlp_loss": ([vp, vp, vp, i64, f64, vp, vp, P(f64), vp], i32),
+    "mlp_adam_step": ([vp, vp, vp, vp, vp, f64, f64, f64, f64, i64, vp], i32),
+    "mlp_windows": ([vp, i32, i32, vp, vp], i32),
+    "mlp_closure": ([vp, i64, f64, vp, vp, vp], i32),
 }
 
 EXPORTS = []

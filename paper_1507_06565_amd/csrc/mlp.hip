@@ -1,0 +1,489 @@
+// Learned closure network of the gray model: forward, backward and Adam on
+// gfx950 matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
+// accumulation).
+//
+// Network: 33 porosities (zero-padded to 64) -> 128 -> 128 -> 128 -> 16 (2
+// used), exact-erf GELU between layers.  A workgroup (4 wavefronts) carries
+// 64 batch rows through every layer; wavefront w owns rows 16w..16w+15 and
+// produces 16x16 output tiles, accumulating over K in steps of 32.
+// Activations live in LDS as BF16 between layers; pre-activations (FP32) and
+// activations (BF16) go to the workspace for the backward pass.
+//
+// Operand layout of one MFMA (16 x 16 output, K = 32): lane l supplies row
+// (A) or column (B) l % 16 and the eight K entries 8*(l/16) .. 8*(l/16)+7;
+// it receives output rows 4*(l/16) .. 4*(l/16)+3 of column l % 16.  A and B
+// use the same K labelling, so the contraction is over all 32 entries.
+//
+// Weights: FP32 master vector (layout in include/mlp.h) plus a BF16 copy in
+// two layouts, row-major [K][N] (for the data gradients dH = dZ W^T) and
+// transposed [N][K] (for the forward products), so that every B operand is
+// one 16-byte load.
+//
+// Backward: per workgroup, data gradients through the layers and per-
+// workgroup partial weight and bias gradients (weight gradients contract
+// over the workgroup's 64 rows on the matrix cores); a second kernel sums
+// the partials over workgroups in a fixed order, so gradients are
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/mlp.h"
+#include "internal.hpp"
+
+namespace lbm {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int IN = 64, HID = 128, OUTP = 16, ROWS = 64, THREADS = 256;
+constexpr int OW1 = 0, OB1 = OW1 + IN * HID, OW2 = OB1 + HID, OB2 = OW2 + HID * HID, OW3 = OB2 + HID,
+              OB3 = OW3 + HID * HID, OW4 = OB3 + HID, OB4 = OW4 + HID * OUTP, NP = OB4 + OUTP;
+static_assert(NP == MLP_NPARAM, "parameter layout");
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_prime(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
+}
+
+__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// out[16w + i][n] for the wave's 16 rows = in[16 rows][K] x W^T; W^T given as
+// [N][K] (contiguous K).  Calls f(row_in_block, col, value) for every output.
+template <int K, class F>
+__device__ __forceinline__ void gemm_rows(const bf16* in, const bf16* WT, int N, F&& f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = 16 * w + (lane & 15), kg = 8 * (lane >> 4);
+    for (int nt = 0; nt < N / 16; ++nt) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < K / 32; ++ks) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(in + r * K + ks * 32 + kg);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(WT + (nt * 16 + (lane & 15)) * K + ks * 32 + kg);
+            acc = mfma(a, b, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f(16 * w + 4 * (lane >> 4) + j, nt * 16 + (lane & 15), acc[j]);
+    }
+}
+
+template <bool TRAIN>
+__global__ void __launch_bounds__(THREADS) k_forward(const float* __restrict__ pf, const bf16* __restrict__ pb,
+                                                     const bf16* __restrict__ x, float* __restrict__ y,
+                                                     float* __restrict__ zws, bf16* __restrict__ hws, int64_t B) {
+    __shared__ __attribute__((aligned(16))) bf16 xin[ROWS * IN];
+    __shared__ __attribute__((aligned(16))) bf16 h[2][ROWS * HID];
+    const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+    const bf16* WT = pb + MLP_NPARAM;  // transposed copy
+    for (int i = threadIdx.x; i < ROWS * IN / 8; i += THREADS)
+        reinterpret_cast<bf16x8*>(xin)[i] = reinterpret_cast<const bf16x8*>(x + row0 * IN)[i];
+    __syncthreads();
+    auto hidden = [&](int layer, const bf16* in_lds, bf16* out_lds, auto kdim, int ow, int ob) {
+        constexpr int K = decltype(kdim)::value;
+        gemm_rows<K>(in_lds, WT + ow, HID, [&](int r, int n, float v) {
+            const float zz = v + pf[ob + n];
+            const float hh = gelu(zz);
+            out_lds[r * HID + n] = (bf16)hh;
+            if (TRAIN) {
+                const int64_t g = (row0 + r) * HID + n;
+                zws[(int64_t)layer * B * HID + g] = zz;
+                hws[(int64_t)layer * B * HID + g] = (bf16)hh;
+            }
+        });
+        __syncthreads();
+    };
+    hidden(0, xin, h[0], std::integral_constant<int, IN>{}, OW1, OB1);
+    hidden(1, h[0], h[1], std::integral_constant<int, HID>{}, OW2, OB2);
+    hidden(2, h[1], h[0], std::integral_constant<int, HID>{}, OW3, OB3);
+    gemm_rows<HID>(h[0], WT + OW4, OUTP,
+                   [&](int r, int n, float v) { y[(row0 + r) * OUTP + n] = v + pf[OB4 + n]; });
+}
+
+// Partial weight gradient of one workgroup: part[ow + k*N + n] =
+// sum_rows A[row][k] * D[row][n] for A [64][K] and D [64][DS] (N <= DS
+// columns used) in LDS; the contraction over the 64 rows runs on the MFMA.
+template <int K, int N, int DS>
+__device__ __forceinline__ void weight_grad(const bf16* A, const bf16* D, float* part, int ow) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kg = 8 * (lane >> 4);
+    constexpr int MT = K / 16, NT = N / 16;
+    for (int t = w; t < MT * NT; t += 4) {
+        const int mt = t / NT, nt = t % NT;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < ROWS / 32; ++ks) {
+            bf16x8 a, b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int row = ks * 32 + kg + j;
+                a[j] = A[row * K + mt * 16 + (lane & 15)];
+                b[j] = D[row * DS + nt * 16 + (lane & 15)];
+            }
+            acc = mfma(a, b, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            part[ow + (mt * 16 + 4 * (lane >> 4) + j) * N + nt * 16 + (lane & 15)] = acc[j];
+    }
+}
+
+// dH[16 rows of the wave][k] = sum_n dZ[row][n] W[k][n]: A = dZ (LDS, [64][N]),
+// B from the row-major W [K][N]; calls f(row, k, value).
+template <int N, class F>
+__device__ __forceinline__ void data_grad(const bf16* dZ, const bf16* W, int K, F&& f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = 16 * w + (lane & 15), kg = 8 * (lane >> 4);
+    for (int kt = 0; kt < K / 16; ++kt) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ns = 0; ns < (N + 31) / 32; ++ns) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(dZ + r * 32 * ((N + 31) / 32) + ns * 32 + kg);
+            bf16x8 b;
+            if (ns * 32 + kg < N)
+                b = *reinterpret_cast<const bf16x8*>(W + (kt * 16 + (lane & 15)) * N + ns * 32 + kg);
+            else
+#pragma unroll
+                for (int j = 0; j < 8; ++j) b[j] = (bf16)0.0f;
+            acc = mfma(a, b, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f(16 * w + 4 * (lane >> 4) + j, kt * 16 + (lane & 15), acc[j]);
+    }
+}
+
+__global__ void __launch_bounds__(THREADS) k_backward(const float* __restrict__ pf, const bf16* __restrict__ pb,
+                                                      const bf16* __restrict__ x, const float* __restrict__ zws,
+                                                      const bf16* __restrict__ hws, const float* __restrict__ dy,
+                                                      float* __restrict__ partials, float* __restrict__ dx,
+                                                      int64_t B) {
+    __shared__ __attribute__((aligned(16))) bf16 act[ROWS * HID];  // activations of the layer below
+    __shared__ __attribute__((aligned(16))) bf16 dz[ROWS * HID];   // gradient at the current layer
+    __shared__ __attribute__((aligned(16))) bf16 dyb[ROWS * 32];   // output gradient, padded to K = 32
+    __shared__ float colsum[4][HID];
+    const int64_t row0 = (int64_t)blockIdx.x * ROWS;
+    float* part = partials + (int64_t)blockIdx.x * MLP_NPARAM;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+
+    // output layer: dY (FP32) -> bias partial of b4, BF16 copy
+    for (int i = threadIdx.x; i < ROWS * 32; i += THREADS) {
+        const int r = i / 32, n = i % 32;
+        dyb[i] = (bf16)(n < OUTP ? dy[(row0 + r) * OUTP + n] : 0.0f);
+    }
+    if (threadIdx.x < OUTP) {
+        float s = 0.f;
+        for (int r = 0; r < ROWS; ++r) s += dy[(row0 + r) * OUTP + threadIdx.x];
+        part[OB4 + threadIdx.x] = s;
+    }
+    auto load_act = [&](int layer) {  // activations H_layer (0-based) into act
+        __syncthreads();
+        for (int i = threadIdx.x; i < ROWS * HID / 8; i += THREADS)
+            reinterpret_cast<bf16x8*>(act)[i] =
+                reinterpret_cast<const bf16x8*>(hws + (int64_t)layer * B * HID + row0 * HID)[i];
+        __syncthreads();
+    };
+    // dW4 = H3^T dY
+    load_act(2);
+    weight_grad<HID, OUTP, 32>(act, dyb, part, OW4);
+
+    // one hidden layer: dH = dNext W_next^T (dNext in `src` with row stride
+    // SS, contraction width NC = the output width of W_next [HID][NC]),
+    // dZ = dH * gelu'(Z) into dz, and the bias partial of the layer
+    auto hidden = [&](int layer, const bf16* src, auto ss, auto nc, int ow_next) {
+        constexpr int SS = decltype(ss)::value, NC = decltype(nc)::value;
+        float dzr[HID / 16][4];
+        const int r = 16 * w + (lane & 15), kg = 8 * (lane >> 4);
+        for (int kt = 0; kt < HID / 16; ++kt) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ns = 0; ns < (NC + 31) / 32; ++ns) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(src + r * SS + ns * 32 + kg);
+                bf16x8 b;
+                if (ns * 32 + kg < NC)
+                    b = *reinterpret_cast<const bf16x8*>(pb + ow_next + (kt * 16 + (lane & 15)) * NC + ns * 32 + kg);
+                else
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) b[j] = (bf16)0.0f;
+                acc = mfma(a, b, acc);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dzr[kt][j] = acc[j];
+        }
+        __syncthreads();  // everyone is done reading src (it may be dz)
+        const float* Z = zws + (int64_t)layer * B * HID;
+        for (int kt = 0; kt < HID / 16; ++kt) {
+            const int col = kt * 16 + (lane & 15);
+            float s4 = 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int rr = 16 * w + 4 * (lane >> 4) + j;
+                const float g = dzr[kt][j] * gelu_prime(Z[(row0 + rr) * HID + col]);
+                dz[rr * HID + col] = (bf16)g;
+                s4 += g;
+            }
+            float v = s4;
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 16) colsum[w][col] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < HID) {
+            const int ob = layer == 0 ? OB1 : (layer == 1 ? OB2 : OB3);
+            part[ob + threadIdx.x] =
+                ((colsum[0][threadIdx.x] + colsum[1][threadIdx.x]) + colsum[2][threadIdx.x]) + colsum[3][threadIdx.x];
+        }
+    };
+    // layer 3 (index 2): from dY through W4
+    hidden(2, dyb, std::integral_constant<int, 32>{}, std::integral_constant<int, OUTP>{}, OW4);
+    load_act(1);
+    weight_grad<HID, HID, HID>(act, dz, part, OW3);
+    // layer 2
+    hidden(1, dz, std::integral_constant<int, HID>{}, std::integral_constant<int, HID>{}, OW3);
+    load_act(0);
+    weight_grad<HID, HID, HID>(act, dz, part, OW2);
+    // layer 1
+    hidden(0, dz, std::integral_constant<int, HID>{}, std::integral_constant<int, HID>{}, OW2);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ROWS * IN / 8; i += THREADS)
+        reinterpret_cast<bf16x8*>(act)[i] = reinterpret_cast<const bf16x8*>(x + row0 * IN)[i];
+    __syncthreads();
+    weight_grad<IN, HID, HID>(act, dz, part, OW1);
+    if (dx) {
+        data_grad<HID>(dz, pb + OW1, IN, [&](int rr, int k, float v) { dx[(row0 + rr) * IN + k] = v; });
+    }
+}
+
+__global__ void k_reduce(const float* __restrict__ partials, int nwg, float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    float s = 0.f;
+    for (int i = 0; i < nwg; ++i) s += partials[(int64_t)i * MLP_NPARAM + p];
+    grad[p] = s;
+}
+
+// master-parameter index -> (row-major index, transposed index or -1)
+__device__ __forceinline__ int transposed_index(int p) {
+    int o, K, N;
+    if (p < OB1) { o = OW1; K = IN; N = HID; }
+    else if (p >= OW2 && p < OB2) { o = OW2; K = HID; N = HID; }
+    else if (p >= OW3 && p < OB3) { o = OW3; K = HID; N = HID; }
+    else if (p >= OW4 && p < OB4) { o = OW4; K = HID; N = OUTP; }
+    else return -1;
+    const int q = p - o, k = q / N, n = q % N;
+    return o + n * K + k;
+}
+
+__global__ void k_pack(const float* __restrict__ pf, bf16* __restrict__ pb) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    const bf16 v = (bf16)pf[p];
+    pb[p] = v;
+    const int t = transposed_index(p);
+    pb[MLP_NPARAM + (t >= 0 ? t : p)] = v;
+}
+
+__global__ void k_adam(float* __restrict__ pf, bf16* __restrict__ pb, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    const float gi = g[p];
+    const float mi = b1 * m[p] + (1.0f - b1) * gi;
+    const float vi = b2 * v[p] + (1.0f - b2) * gi * gi;
+    m[p] = mi;
+    v[p] = vi;
+    const float w = pf[p] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    pf[p] = w;
+    const bf16 bw = (bf16)w;
+    pb[p] = bw;
+    const int t = transposed_index(p);
+    pb[MLP_NPARAM + (t >= 0 ? t : p)] = bw;
+}
+
+// masked MSE over the two used outputs; dy = 2 mask (y - t) / sum(mask);
+// loss partials per block of 256 rows in a fixed order.
+__global__ void k_loss(const float* __restrict__ y, const float* __restrict__ t, const float* __restrict__ mk,
+                       int64_t B, float inv_n, float* __restrict__ dy, double* __restrict__ lpart) {
+    __shared__ double red[256];
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double l = 0.0;
+    if (r < B) {
+        for (int n = 0; n < OUTP; ++n) {
+            float d = 0.f;
+            if (n < 2) {
+                const float e = (y[r * OUTP + n] - t[r * 2 + n]) * mk[r * 2 + n];
+                d = 2.0f * e * inv_n;
+                l += (double)e * e;
+            }
+            dy[r * OUTP + n] = d;
+        }
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] * inv_n;
+}
+
+// windows of 33 porosities around every cell of ncols columns of height nz,
+// replicate padding; x[(col*nz + z)*64 + j]
+__global__ void k_windows(const double* __restrict__ eps, int nz, int64_t n, bf16* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * IN) return;
+    const int64_t cell = i / IN;
+    const int j = (int)(i % IN);
+    const int64_t col = cell / nz;
+    const int z = (int)(cell % nz);
+    float v = 0.0f;
+    if (j < 33) {
+        int zz = z + j - 16;
+        zz = zz < 0 ? 0 : (zz > nz - 1 ? nz - 1 : zz);
+        v = (float)eps[col * nz + zz];
+    }
+    x[i] = (bf16)v;
+}
+
+__global__ void k_closure(const float* __restrict__ y, int64_t n, double nu, double* __restrict__ nu_eff,
+                          double* __restrict__ drag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double o1 = y[i * OUTP], o2 = y[i * OUTP + 1];
+    nu_eff[i] = nu * exp(o1);
+    drag[i] = o2 > 0 ? o2 + log1p(exp(-o2)) : log1p(exp(o2));
+}
+
+int64_t nwg_of(int64_t B) { return B / ROWS; }
+
+#define MCHK(expr, what)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return set_error(LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+lbm_status check_batch(int64_t B) {
+    if (B <= 0 || B % ROWS != 0 || B > ((int64_t)1 << 26))
+        return set_error(LBM_E_INVAL, "batch size must be a positive multiple of 64");
+    return LBM_OK;
+}
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+lbm_status mlp_workspace_bytes(int64_t B, int64_t* bytes) {
+    lbm_status s = check_batch(B);
+    if (s != LBM_OK || !bytes) return s != LBM_OK ? s : set_error(LBM_E_INVAL, "null pointer");
+    *bytes = B * HID * 3 * 4 + B * HID * 3 * 2 + nwg_of(B) * (int64_t)MLP_NPARAM * 4;
+    return LBM_OK;
+}
+
+lbm_status mlp_pack_bf16(const float* params, void* params_bf16, void* stream) {
+    if (!params || !params_bf16) return set_error(LBM_E_INVAL, "null pointer");
+    k_pack<<<(MLP_NPARAM + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, (bf16*)params_bf16);
+    MCHK(hipGetLastError(), "pack");
+    MCHK(hipStreamSynchronize((hipStream_t)stream), "synchronise");
+    return LBM_OK;
+}
+
+lbm_status mlp_forward(const float* params, const void* params_bf16, const void* x_bf16, int64_t B, float* y,
+                       void* ws, void* stream) {
+    lbm_status s = check_batch(B);
+    if (s != LBM_OK) return s;
+    if (!params || !params_bf16 || !x_bf16 || !y) return set_error(LBM_E_INVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned grid = (unsigned)nwg_of(B);
+    if (ws) {
+        float* z = (float*)ws;
+        bf16* h = (bf16*)((char*)ws + B * HID * 3 * 4);
+        k_forward<true><<<grid, THREADS, 0, st>>>(params, (const bf16*)params_bf16, (const bf16*)x_bf16, y, z, h, B);
+    } else {
+        k_forward<false><<<grid, THREADS, 0, st>>>(params, (const bf16*)params_bf16, (const bf16*)x_bf16, y, nullptr,
+                                                   nullptr, B);
+    }
+    MCHK(hipGetLastError(), "forward");
+    MCHK(hipStreamSynchronize(st), "synchronise");
+    return LBM_OK;
+}
+
+lbm_status mlp_backward(const float* params, const void* params_bf16, const void* x_bf16, void* ws, const float* dy,
+                        int64_t B, float* grad, float* dx, void* stream) {
+    lbm_status s = check_batch(B);
+    if (s != LBM_OK) return s;
+    if (!params || !params_bf16 || !x_bf16 || !ws || !dy || !grad) return set_error(LBM_E_INVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nwg = nwg_of(B);
+    const float* z = (const float*)ws;
+    const bf16* h = (const bf16*)((const char*)ws + B * HID * 3 * 4);
+    float* part = (float*)((char*)ws + B * HID * 3 * 4 + B * HID * 3 * 2);
+    k_backward<<<(unsigned)nwg, THREADS, 0, st>>>(params, (const bf16*)params_bf16, (const bf16*)x_bf16, z, h, dy,
+                                                  part, dx, B);
+    MCHK(hipGetLastError(), "backward");
+    k_reduce<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(part, (int)nwg, grad);
+    MCHK(hipGetLastError(), "gradient reduction");
+    MCHK(hipStreamSynchronize(st), "synchronise");
+    return LBM_OK;
+}
+
+lbm_status mlp_loss(const float* y, const float* target, const float* mask, int64_t B, double mask_sum, float* dy,
+                    double* loss_partials, double* loss, void* stream) {
+    lbm_status s = check_batch(B);
+    if (s != LBM_OK) return s;
+    if (!y || !target || !mask || !dy || !loss_partials) return set_error(LBM_E_INVAL, "null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned nb = (unsigned)((B + 255) / 256);
+    const float inv = (float)(1.0 / (mask_sum > 1.0 ? mask_sum : 1.0));
+    k_loss<<<nb, 256, 0, st>>>(y, target, mask, B, inv, dy, loss_partials);
+    MCHK(hipGetLastError(), "loss");
+    if (loss) {
+        std::vector<double> h(nb);
+        MCHK(hipMemcpyAsync(h.data(), loss_partials, nb * 8, hipMemcpyDeviceToHost, st), "copy loss");
+        MCHK(hipStreamSynchronize(st), "synchronise");
+        double L = 0;
+        for (double v : h) L += v;
+        *loss = L;
+    } else {
+        MCHK(hipStreamSynchronize(st), "synchronise");
+    }
+    return LBM_OK;
+}
+
+lbm_status mlp_adam_step(float* params, void* params_bf16, float* m, float* v, const float* grad, double lr,
+                         double b1, double b2, double eps, int64_t t, void* stream) {
+    if (!params || !params_bf16 || !m || !v || !grad || t < 1) return set_error(LBM_E_INVAL, "bad arguments");
+    const float c1 = (float)(1.0 - std::pow(b1, (double)t)), c2 = (float)(1.0 - std::pow(b2, (double)t));
+    k_adam<<<(MLP_NPARAM + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, (bf16*)params_bf16, m, v, grad,
+                                                                       (float)lr, (float)b1, (float)b2, (float)eps,
+                                                                       c1, c2);
+    MCHK(hipGetLastError(), "adam");
+    MCHK(hipStreamSynchronize((hipStream_t)stream), "synchronise");
+    return LBM_OK;
+}
+
+lbm_status mlp_windows(const double* eps, int32_t ncols, int32_t nz, void* x_bf16, void* stream) {
+    if (!eps || !x_bf16 || ncols < 1 || nz < 1) return set_error(LBM_E_INVAL, "bad arguments");
+    const int64_t n = (int64_t)ncols * nz;
+    k_windows<<<(unsigned)((n * IN + 255) / 256), 256, 0, (hipStream_t)stream>>>(eps, nz, n, (bf16*)x_bf16);
+    MCHK(hipGetLastError(), "windows");
+    MCHK(hipStreamSynchronize((hipStream_t)stream), "synchronise");
+    return LBM_OK;
+}
+
+lbm_status mlp_closure(const float* y, int64_t n, double nu, double* nu_eff, double* drag, void* stream) {
+    if (!y || !nu_eff || !drag || n < 1 || !(nu > 0)) return set_error(LBM_E_INVAL, "bad arguments");
+    k_closure<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(y, n, nu, nu_eff, drag);
+    MCHK(hipGetLastError(), "closure");
+    MCHK(hipStreamSynchronize((hipStream_t)stream), "synchronise");
+    return LBM_OK;
+}
+
+}  // extern "C"
