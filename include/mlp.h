@@ -73,9 +73,11 @@ lbm_status mlp_adam_step(float* params, void* params_bf16, float* m, float* v, c
  * eps [ncols*nz] FP64 -> x_bf16 [ncols*nz][64]. */
 lbm_status mlp_windows(const double* eps, int32_t ncols, int32_t nz, void* x_bf16, void* stream);
 
-/* Closure coefficients from the outputs: nu_eff = nu exp(o1), drag =
- * softplus(o2), n rows, FP64 outputs. */
-lbm_status mlp_closure(const float* y, int64_t n, double nu, double* nu_eff, double* drag, void* stream);
+/* Closure coefficients from the outputs of n rows and the cells' own
+ * porosities eps[n]: nu_eff = nu exp((1 - eps) o1), drag = (1 - eps)
+ * softplus(o2); FP64 outputs. */
+lbm_status mlp_closure(const float* y, const double* eps, int64_t n, double nu, double* nu_eff, double* drag,
+                       void* stream);
 
 #ifdef __cplusplus
 }

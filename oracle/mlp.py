@@ -1,8 +1,9 @@
 """Plain FP64 reference of the learned closure network (test infrastructure).
 
 The closure maps a window of 33 planar porosities (replicate padding at the
-column ends) to two local coefficients of the gray model of Sec. 4:
-    nu_eff / nu = exp(o1),    eps nu / K = softplus(o2).
+column ends) to two local coefficients of the gray model of Sec. 4 (eps_c is
+the porosity of the cell itself; both reduce to the free-fluid values at 1):
+    nu_eff / nu = exp((1 - eps_c) o1),    eps nu / K = (1 - eps_c) softplus(o2).
 Network: 33 inputs (zero-padded to 64) -> 128 -> 128 -> 128 -> 16 outputs
 (2 used), exact-erf GELU between layers, linear output.
 
@@ -117,10 +118,11 @@ def windows(eps_profile, half=16):
     return X
 
 
-def closure(Y, nu):
-    """(nu_eff, drag) from the two network outputs."""
+def closure(Y, eps_c, nu):
+    """(nu_eff, drag) from the two network outputs and the cells' porosity."""
     o1, o2 = Y[:, 0], Y[:, 1]
-    return nu * np.exp(o1), np.logaddexp(0.0, o2)
+    s = 1.0 - np.asarray(eps_c, dtype=np.float64)
+    return nu * np.exp(s * o1), s * np.logaddexp(0.0, o2)
 
 
 def bf16_round(a):

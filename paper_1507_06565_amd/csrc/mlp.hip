@@ -350,13 +350,14 @@ __global__ void k_windows(const double* __restrict__ eps, int nz, int64_t n, bf1
     x[i] = (bf16)v;
 }
 
-__global__ void k_closure(const float* __restrict__ y, int64_t n, double nu, double* __restrict__ nu_eff,
-                          double* __restrict__ drag) {
+__global__ void k_closure(const float* __restrict__ y, const double* __restrict__ eps, int64_t n, double nu,
+                          double* __restrict__ nu_eff, double* __restrict__ drag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double o1 = y[i * OUTP], o2 = y[i * OUTP + 1];
-    nu_eff[i] = nu * exp(o1);
-    drag[i] = o2 > 0 ? o2 + log1p(exp(-o2)) : log1p(exp(o2));
+    const double s = 1.0 - eps[i];  // vanishes in free fluid
+    nu_eff[i] = nu * exp(s * o1);
+    drag[i] = s * (o2 > 0 ? o2 + log1p(exp(-o2)) : log1p(exp(o2)));
 }
 
 int64_t nwg_of(int64_t B) { return B / ROWS; }
@@ -478,9 +479,10 @@ lbm_status mlp_windows(const double* eps, int32_t ncols, int32_t nz, void* x_bf1
     return LBM_OK;
 }
 
-lbm_status mlp_closure(const float* y, int64_t n, double nu, double* nu_eff, double* drag, void* stream) {
-    if (!y || !nu_eff || !drag || n < 1 || !(nu > 0)) return set_error(LBM_E_INVAL, "bad arguments");
-    k_closure<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(y, n, nu, nu_eff, drag);
+lbm_status mlp_closure(const float* y, const double* eps, int64_t n, double nu, double* nu_eff, double* drag,
+                       void* stream) {
+    if (!y || !eps || !nu_eff || !drag || n < 1 || !(nu > 0)) return set_error(LBM_E_INVAL, "bad arguments");
+    k_closure<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(y, eps, n, nu, nu_eff, drag);
     MCHK(hipGetLastError(), "closure");
     MCHK(hipStreamSynchronize((hipStream_t)stream), "synchronise");
     return LBM_OK;

@@ -106,5 +106,6 @@ class ClosureNet:
         y = self.forward(x)
         nue = torch.empty(n, dtype=torch.float64, device=self.dev)
         drag = torch.empty(n, dtype=torch.float64, device=self.dev)
-        check(lib.mlp_closure(_p(y), n, nu, _p(nue), _p(drag), self.s), "mlp_closure")
+        e = torch.from_numpy(np.ascontiguousarray(eps_cols, dtype=np.float64).ravel()).to(self.dev)
+        check(lib.mlp_closure(_p(y), _p(e), n, nu, _p(nue), _p(drag), self.s), "mlp_closure")
         return nue.cpu().numpy().reshape(eps_cols.shape), drag.cpu().numpy().reshape(eps_cols.shape)

@@ -105,7 +105,7 @@ def test_windows_and_closure():
     assert np.array_equal(xw, R.bf16_round(want))
     nue, drag = net.closure(eps, 0.1)
     y = net.forward(x).cpu().numpy().astype(np.float64)[:n]
-    ne, dr = R.closure(y, 0.1)
+    ne, dr = R.closure(y, eps.ravel(), 0.1)
     assert np.allclose(nue.ravel(), ne, rtol=1e-12) and np.allclose(drag.ravel(), dr, rtol=1e-12, atol=1e-300)
 
 

@@ -91,6 +91,9 @@ def test_closure_map():
     Y = np.zeros((3, 16))
     Y[:, 0] = [0.0, math.log(2.0), -1.0]
     Y[:, 1] = [0.0, 20.0, -20.0]
-    nue, drag = mlp.closure(Y, 0.1)
+    nue, drag = mlp.closure(Y, np.zeros(3), 0.1)
     assert np.allclose(nue, [0.1, 0.2, 0.1 * math.exp(-1)])
     assert np.allclose(drag, [math.log(2.0), 20.0 + math.log1p(math.exp(-20)), math.log1p(math.exp(-20))])
+    nue, drag = mlp.closure(Y, np.array([1.0, 0.5, 1.0]), 0.1)
+    assert nue[0] == 0.1 and nue[2] == 0.1 and drag[0] == 0 and drag[2] == 0
+    assert np.isclose(nue[1], 0.1 * math.sqrt(2.0)) and np.isclose(drag[1], 0.5 * (20.0 + math.log1p(math.exp(-20))))
