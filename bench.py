@@ -215,7 +215,7 @@ def main():
 def _sweep_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("sweep.hip", "internal.hpp", "lattice.hpp"):
+    for f in ("sweep.hip", "cell.hpp", "internal.hpp", "lattice.hpp"):
         with open(os.path.join(ROOT, "paper_1507_06565_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
