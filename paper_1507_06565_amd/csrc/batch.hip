@@ -148,10 +148,10 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
                 if (c < N) {
                     const int x = c % nx, t = c / nx, y = t % ny, z = t / ny;
                     if (even)
-                        ux = cell_update<L_AA, P_EVEN, BC, false>(pa, nullptr, info, segbase, lparam, a.k, nx, ny,
+                        ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, nullptr, info, segbase, lparam, a.k, nx, ny,
                                                                   nz, c, x, y, z);
                     else
-                        ux = cell_update<L_AA, P_ODD, BC, false>(pa, nullptr, info, segbase, lparam, a.k, nx, ny, nz,
+                        ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, nullptr, info, segbase, lparam, a.k, nx, ny, nz,
                                                                  c, x, y, z);
                 }
                 if (check) {

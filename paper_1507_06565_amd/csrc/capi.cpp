@@ -175,6 +175,24 @@ CellConsts lbm::make_consts(const lbm_params& p, double wp, double wm, const dou
     k.rho0 = (float)p.rho0;
     k.inv_rho0 = (float)(1.0 / p.rho0);
     for (int i = 0; i < 3; ++i) k.F[i] = (float)p.force[i];
+    for (int i = 0; i < 3; ++i) k.fh[i] = (float)(0.5 * p.force[i] / p.rho0);
+    const double cp = 1.0 - 0.5 * wp, cm = 1.0 - 0.5 * wm;
+    k.om1 = (float)(1.0 - wp);
+    k.hp = (float)(-0.5 * wp);
+    k.hm = (float)(-0.5 * wm);
+    k.a_uu = (float)(-1.5 * wp * p.rho0);
+    k.a_uF = (float)(-3.0 * cp);
+    for (int c = 0; c < 2; ++c) {
+        const double w = c == 0 ? 1.0 / 18.0 : 1.0 / 36.0;
+        k.beta[c] = (float)(4.5 * wp * w * p.rho0);
+        k.delta[c] = (float)(3.0 * wm * w * p.rho0);
+    }
+    for (int pr = 0; pr < 9; ++pr) {
+        const int j = 2 * pr + 1;
+        const double eF = D3Q19::ex[j] * p.force[0] + D3Q19::ey[j] * p.force[1] + D3Q19::ez[j] * p.force[2];
+        k.gam[pr] = (float)(9.0 * cp * weight(j) * eF);
+        k.zet[pr] = (float)(3.0 * cm * weight(j) * eF);
+    }
     for (int j = 0; j < Q; ++j) {
         const double eu = D3Q19::ex[j] * wall_velocity[0] + D3Q19::ey[j] * wall_velocity[1] +
                           D3Q19::ez[j] * wall_velocity[2];

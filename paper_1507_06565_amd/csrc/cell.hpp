@@ -61,10 +61,20 @@ __device__ __forceinline__ void bb_coeffs(float prm, float& c1, float& c0, float
     }
 }
 
-// TRT collision with Guo forcing split into even/odd parts, in place on g.
+// TRT collision with the Guo forcing split into even and odd parts
+// (eqs. (TRT), (TRT2), (equilibrium), (collision)), in place on g.
+//
+// With s = g_k + g_kbar, d = g_k - g_kbar, eu = e_k.u and w the weight of k,
+// the post-collision pair is g_k + P + M and g_kbar + P - M, where
+//   P = -omega+/2 s + w a + eu (4.5 omega+ w rho0 eu + 9 (1-omega+/2) w e_k.F)
+//   M = -omega-/2 d + 3 omega- w rho0 eu + 3 (1-omega-/2) w e_k.F
+//   a = omega+ drho - 1.5 omega+ rho0 u.u - 3 (1-omega+/2) u.F,
+// which is the textbook form -omega+(g+ - eq+) + (1-omega+/2) S+ and
+// -omega-(g- - eq-) + (1-omega-/2) S- with the uniform factors folded; the
+// rest population becomes (1-omega+) g_0 + a/3.  FMAs are explicit and no
+// other contraction is allowed, so every kernel that inlines this rounds
+// identically and all of them agree bit for bit.
 __device__ __forceinline__ float collide(float (&g)[Q], const CellConsts& a) {
-    // no FP contraction: every kernel that inlines this evaluates the same
-    // sequence of roundings, so all of them agree bit for bit
 #pragma clang fp contract(off)
     float drho = g[0];
     float jx = 0.f, jy = 0.f, jz = 0.f;
@@ -74,37 +84,36 @@ __device__ __forceinline__ float collide(float (&g)[Q], const CellConsts& a) {
         const float s = g[k] + g[k + 1];
         const float d = g[k] - g[k + 1];
         drho += s;
-        if (L::ex[k]) jx += L::ex[k] * d;
-        if (L::ey[k]) jy += L::ey[k] * d;
-        if (L::ez[k]) jz += L::ez[k] * d;
+        if (L::ex[k]) jx = L::ex[k] > 0 ? jx + d : jx - d;
+        if (L::ey[k]) jy = L::ey[k] > 0 ? jy + d : jy - d;
+        if (L::ez[k]) jz = L::ez[k] > 0 ? jz + d : jz - d;
     }
-    const float ux = (jx + 0.5f * a.F[0]) * a.inv_rho0;
-    const float uy = (jy + 0.5f * a.F[1]) * a.inv_rho0;
-    const float uz = (jz + 0.5f * a.F[2]) * a.inv_rho0;
-    const float uu = ux * ux + uy * uy + uz * uz;
-    const float uF = ux * a.F[0] + uy * a.F[1] + uz * a.F[2];
-    {
-        const float w0 = 1.0f / 3.0f;
-        const float eq = w0 * (drho - 1.5f * a.rho0 * uu);
-        g[0] = g[0] - a.wp * (g[0] - eq) + a.cp * (w0 * (-3.0f * uF));
-    }
+    const float ux = __builtin_fmaf(jx, a.inv_rho0, a.fh[0]);
+    const float uy = __builtin_fmaf(jy, a.inv_rho0, a.fh[1]);
+    const float uz = __builtin_fmaf(jz, a.inv_rho0, a.fh[2]);
+    const float uu = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    const float uF = __builtin_fmaf(ux, a.F[0], __builtin_fmaf(uy, a.F[1], uz * a.F[2]));
+    const float aa = __builtin_fmaf(a.a_uu, uu, __builtin_fmaf(a.a_uF, uF, a.wp * drho));
+    const float al0 = aa * (1.0f / 3.0f);
+    const float al1 = aa * (1.0f / 18.0f);
+    const float al2 = aa * (1.0f / 36.0f);
+    g[0] = __builtin_fmaf(a.om1, g[0], al0);
 #pragma unroll
     for (int p = 0; p < 9; ++p) {
         const int k = 2 * p + 1;
-        const float w = (float)weight(k);
-        const float eu = L::ex[k] * ux + L::ey[k] * uy + L::ez[k] * uz;
-        const float eF = L::ex[k] * a.F[0] + L::ey[k] * a.F[1] + L::ez[k] * a.F[2];
-        const float eqp = w * (drho + a.rho0 * (4.5f * eu * eu - 1.5f * uu));
-        const float eqm = w * (3.0f * a.rho0 * eu);
-        const float gp = 0.5f * (g[k] + g[k + 1]);
-        const float gm = 0.5f * (g[k] - g[k + 1]);
-        const float sp = w * (9.0f * eu * eF - 3.0f * uF);
-        const float sm = w * (3.0f * eF);
-        const float dp = -a.wp * (gp - eqp) + a.cp * sp;
-        const float dm = -a.wm * (gm - eqm) + a.cm * sm;
+        const int c = p < 3 ? 0 : 1;
+        float eu = 0.0f;
+        if (L::ex[k]) eu = L::ex[k] > 0 ? eu + ux : eu - ux;
+        if (L::ey[k]) eu = L::ey[k] > 0 ? eu + uy : eu - uy;
+        if (L::ez[k]) eu = L::ez[k] > 0 ? eu + uz : eu - uz;
         const float gk = g[k], gkb = g[k + 1];
-        g[k] = gk + dp + dm;
-        g[k + 1] = gkb + dp - dm;
+        const float s = gk + gkb;
+        const float d = gk - gkb;
+        const float P = __builtin_fmaf(eu, __builtin_fmaf(a.beta[c], eu, a.gam[p]),
+                                       __builtin_fmaf(a.hp, s, c == 0 ? al1 : al2));
+        const float M = __builtin_fmaf(a.hm, d, __builtin_fmaf(a.delta[c], eu, a.zet[p]));
+        g[k] = (gk + P) + M;
+        g[k + 1] = (gkb + P) - M;
     }
     return ux;
 }
@@ -134,7 +143,7 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 // One cell of one time step: pull (with the partial bounce-back values),
 // link correction, collision, push and the next step's partial values.
 // Returns the x-velocity of this step's moments (0 for a solid cell).
-template <int LAYOUT, int PARITY, int BC, bool NT>
+template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD>
 __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb, const uint32_t* __restrict__ info,
                                              const int32_t* __restrict__ segbase,
                                              const float* __restrict__ lparam, const CellConsts& K, int nx,
@@ -176,8 +185,8 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
 
     // 2) links: the pulled value of an unknown population is the partial
     //    value P stored last step; add c0 times the second node's value
+    float prm[Q];
     if (mask) {
-        float prm[Q];
         const int base = segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
         // every coefficient load is issued before any is used, without
         // branches: for a direction that is not a link the rank points at a
@@ -216,9 +225,9 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
         else
             AT(D, k, NB(L::ex[k], L::ey[k], L::ez[k])) = g[k];
     }
-    // 5) partial bounce-back values for the next step; the coefficients are
-    //    read again (a cache hit) rather than held in registers across the
-    //    collision
+    // 5) partial bounce-back values for the next step; with RELOAD the
+    //    coefficients are read again (a cache hit) rather than held in
+    //    registers across the collision, for kernels short of registers
     if (mask) {
         const int base = segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
         const __attribute__((address_space(1))) char* lp = (const __attribute__((address_space(1))) char*)lparam;
@@ -226,8 +235,11 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
         for (int k = 1; k < Q; ++k) {
             const int kk = opp(k);
             if (mask & (1u << (kk - 1))) {
-                const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
-                const float pk = __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)(lp + (li << 2)));
+                float pk = prm[k];
+                if (RELOAD) {
+                    const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
+                    pk = __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)(lp + (li << 2)));
+                }
                 float c1, c0, cb;
                 bb_coeffs<BC>(pk, c1, c0, cb);
                 const float P = c1 * g[kk] + cb * g[k] + (pk != pk ? K.wterm[k] : 0.0f);

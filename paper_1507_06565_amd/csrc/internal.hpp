@@ -46,11 +46,23 @@ enum Layout : int { L_TWOGRID = 0, L_AA = 1 };
 enum Parity : int { P_EVEN = 0, P_ODD = 1 };
 
 // collision constants shared by every cell of a run
+// Uniform constants of the cell update.  The TRT collision with the split
+// Guo forcing is evaluated in a folded form (see collide() in cell.hpp); the
+// folded coefficients below are products of the relaxation rates, weights,
+// rho0 and the body force, formed once on the host in FP64.
 struct CellConsts {
     float wp, wm;         // omega+, omega-
     float cp, cm;         // 1 - omega+/2, 1 - omega-/2
     float rho0, inv_rho0;
     float F[3];
+    float fh[3];          // F / (2 rho0)
+    float om1;            // 1 - omega+
+    float hp, hm;         // -omega+/2, -omega-/2
+    float a_uu, a_uF;     // -1.5 omega+ rho0, -3 (1 - omega+/2)
+    float beta[2];        // 4.5 omega+ w rho0 for w = 1/18, 1/36
+    float delta[2];       // 3 omega- w rho0 for w = 1/18, 1/36
+    float gam[9];         // 9 (1 - omega+/2) w_k e_k.F for k = 1, 3, ..., 17
+    float zet[9];         // 3 (1 - omega-/2) w_k e_k.F for k = 1, 3, ..., 17
     float wterm[Q];       // 6 w_k rho0 e_k.u_w for the moving wall
 };
 

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepArgs a) {
         y = t % ny;
         z = t / ny;
     }
-    (void)cell_update<LAYOUT, PARITY, BC, NT>(a.pa, a.pb, a.info, a.segbase, a.lparam, a.k, nx, ny, nz, c, x, y,
+    (void)cell_update<LAYOUT, PARITY, BC, NT, false>(a.pa, a.pb, a.info, a.segbase, a.lparam, a.k, nx, ny, nz, c, x, y,
                                               z);
 }
 
