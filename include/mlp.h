@@ -5,8 +5,10 @@
  * The network maps a window of 33 planar porosities around a cell of a gray
  * column (Sec. 4 of the paper, Fattahi et al., arXiv 1507.06565: the model's
  * effective viscosity and permeability are local functions of the porous
- * structure; the paper uses nu_eff = nu / eps) to two local coefficients:
- *     nu_eff / nu = exp(o1),     eps nu / K = softplus(o2).
+ * structure; the paper uses nu_eff = nu / eps) to two local coefficients,
+ * with eps_c the porosity of the cell itself:
+ *     nu_eff / nu = exp((1 - eps_c) o1),   eps nu / K = (1 - eps_c) softplus(o2),
+ * so that both are exactly the free-fluid values (nu, 0) where eps_c = 1.
  * Layers: 33 inputs (zero-padded to 64) -> 128 -> 128 -> 128 -> 16 outputs
  * (o1, o2 used), exact-erf GELU between layers, linear output.
  *
@@ -78,6 +80,25 @@ lbm_status mlp_windows(const double* eps, int32_t ncols, int32_t nz, void* x_bf1
  * softplus(o2); FP64 outputs. */
 lbm_status mlp_closure(const float* y, const double* eps, int64_t n, double nu, double* nu_eff, double* drag,
                        void* stream);
+
+/* Loss of nprof porosity profiles through the steady gray column and its
+ * gradient with respect to the network outputs (the training signal of the
+ * closure; Sec. 4, eq. (GeneralizedPor2) with the porous force of eq.
+ * (PorousForce), Stokes regime).  Rows p*nz + z (z = 0..nz-1) of y [.][16]
+ * belong to cell z of profile p; eps and u_target [nprof*nz] FP64 are the
+ * planar porosity and the superficial velocity of the pore-scale run; layers
+ * 0 and nz-1 are walls (their values are ignored).  With the closure map
+ * above, the steady profile U of
+ *     d/dz (nu_eff dU/dz) - drag U + eps G = 0,   U = 0 at both walls,
+ * (three-point scheme on cells 1..nz-2, face viscosity the mean of the two
+ * cells, quadratic one-sided slope at the walls, which reproduces the lattice
+ * scheme's parabola exactly) is solved in FP64, and
+ *     loss[p] = weight / nprof * sum_z (U - u_target)^2 / sum_z u_target^2.
+ * dy receives dL/dy for those rows (columns 0 and 1; other columns and the
+ * wall rows 0), by the adjoint of the tridiagonal system.  5 <= nz <= 1024;
+ * loss is a device array of nprof doubles.  One workgroup per profile. */
+lbm_status mlp_profile_loss(const float* y, const double* eps, const double* u_target, int32_t nprof, int32_t nz,
+                            double nu, double G, double weight, float* dy, double* loss, void* stream);
 
 #ifdef __cplusplus
 }

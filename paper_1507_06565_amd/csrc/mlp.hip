@@ -360,6 +360,106 @@ __global__ void k_closure(const float* __restrict__ y, const double* __restrict_
     drag[i] = s * (o2 > 0 ? o2 + log1p(exp(-o2)) : log1p(exp(o2)));
 }
 
+// Profile loss through the steady gray column.  For shear flow along x the
+// steady state of the gray model (eq. (GeneralizedPor2) with the porous force
+// of eq. (PorousForce), Forchheimer term zero) obeys, cell by cell,
+//     d/dz (nu_eff dU/dz) - drag U + eps G = 0,
+// discretised on the cells 1..n (n = nz-2) between the wall layers with face
+// viscosities (nu_i + nu_{i+1})/2 and, next to each wall (U = 0 half a cell
+// away), the one-sided slope 3 U_1 - U_2 / 3, which is exact for the
+// parabola the lattice scheme reproduces.  One workgroup per profile: the
+// lanes form the coefficients, lane 0 runs the two tridiagonal (Thomas)
+// solves -- A U = -eps G and the adjoint A^T lambda = dL/dU -- and the lanes
+// chain dL/dA = -lambda U^T through the closure map into dL/do1, dL/do2.
+constexpr int PL_MAX = 1024;
+
+__device__ __forceinline__ double softplus_d(double o) { return o > 0 ? o + log1p(exp(-o)) : log1p(exp(o)); }
+__device__ __forceinline__ double sigmoid_d(double o) {
+    return o >= 0 ? 1.0 / (1.0 + exp(-o)) : exp(o) / (1.0 + exp(o));
+}
+
+__global__ void __launch_bounds__(64) k_profile_loss(const float* __restrict__ y, const double* __restrict__ eps,
+                                                     const double* __restrict__ ut, int nz, double nu, double G,
+                                                     double scale, float* __restrict__ dy,
+                                                     double* __restrict__ loss) {
+    __shared__ double snu[PL_MAX], sd[PL_MAX], su[PL_MAX], sl[PL_MAX], cpr[PL_MAX], dpr[PL_MAX];
+    const int p = blockIdx.x;
+    const int n = nz - 2;
+    const int64_t r0 = (int64_t)p * nz;
+    // coefficients of the interior cells (index i = z - 1)
+    for (int i = threadIdx.x; i < n; i += 64) {
+        const int64_t r = r0 + i + 1;
+        const double s = 1.0 - eps[r];
+        snu[i] = nu * exp(s * (double)y[r * OUTP]);
+        sd[i] = s * softplus_d((double)y[r * OUTP + 1]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // tridiagonal rows: a (sub), b (diagonal), c (super)
+        auto fa = [&](int i) { return i == 0 ? 0.0 : 0.5 * (snu[i - 1] + snu[i]) + (i == n - 1 ? snu[i] / 3.0 : 0.0); };
+        auto fc = [&](int i) { return i == n - 1 ? 0.0 : 0.5 * (snu[i] + snu[i + 1]) + (i == 0 ? snu[i] / 3.0 : 0.0); };
+        auto fb = [&](int i) {
+            double b = -sd[i];
+            if (i > 0) b -= 0.5 * (snu[i - 1] + snu[i]);
+            else b -= 3.0 * snu[i];
+            if (i < n - 1) b -= 0.5 * (snu[i] + snu[i + 1]);
+            else b -= 3.0 * snu[i];
+            return b;
+        };
+        // A U = -eps G
+        for (int i = 0; i < n; ++i) {
+            const double ai = fa(i), bi = fb(i), ci = fc(i);
+            const double ri = -eps[r0 + i + 1] * G;
+            const double m = i == 0 ? bi : bi - ai * cpr[i - 1];
+            cpr[i] = ci / m;
+            dpr[i] = (i == 0 ? ri : ri - ai * dpr[i - 1]) / m;
+        }
+        su[n - 1] = dpr[n - 1];
+        for (int i = n - 2; i >= 0; --i) su[i] = dpr[i] - cpr[i] * su[i + 1];
+        // loss and dL/dU
+        double tt = 0.0, ee = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double t = ut[r0 + i + 1];
+            const double e = su[i] - t;
+            tt += t * t;
+            ee += e * e;
+        }
+        const double w = scale / (tt > 0 ? tt : 1.0);
+        loss[p] = w * ee;
+        // A^T lambda = dL/dU: sub-diagonal of A^T is c(i-1), super is a(i+1)
+        for (int i = 0; i < n; ++i) {
+            const double ai = i == 0 ? 0.0 : fc(i - 1), bi = fb(i), ci = i == n - 1 ? 0.0 : fa(i + 1);
+            const double ri = 2.0 * w * (su[i] - ut[r0 + i + 1]);
+            const double m = i == 0 ? bi : bi - ai * cpr[i - 1];
+            cpr[i] = ci / m;
+            dpr[i] = (i == 0 ? ri : ri - ai * dpr[i - 1]) / m;
+        }
+        sl[n - 1] = dpr[n - 1];
+        for (int i = n - 2; i >= 0; --i) sl[i] = dpr[i] - cpr[i] * sl[i + 1];
+    }
+    __syncthreads();
+    // dL/dnu_i and dL/ddrag_i, chained through the closure map
+    for (int z = threadIdx.x; z < nz; z += 64) {
+        const int64_t r = r0 + z;
+        float d1 = 0.f, d2 = 0.f;
+        if (z >= 1 && z <= n) {
+            const int i = z - 1;
+            const double li = sl[i], ui = su[i];
+            double gnu = 0.0;
+            // faces: dL/df = (lambda_i - lambda_j)(U_i - U_j), half to each cell
+            if (i > 0) gnu += 0.5 * (li - sl[i - 1]) * (ui - su[i - 1]);
+            else gnu += li * (3.0 * ui - su[1] / 3.0);
+            if (i < n - 1) gnu += 0.5 * (li - sl[i + 1]) * (ui - su[i + 1]);
+            else gnu += li * (3.0 * ui - su[n - 2] / 3.0);
+            const double gd = li * ui;
+            const double s = 1.0 - eps[r];
+            d1 = (float)(gnu * snu[i] * s);
+            d2 = (float)(gd * s * sigmoid_d((double)y[r * OUTP + 1]));
+        }
+        for (int c = 0; c < OUTP; ++c) dy[r * OUTP + c] = c == 0 ? d1 : (c == 1 ? d2 : 0.f);
+    }
+}
+
 int64_t nwg_of(int64_t B) { return B / ROWS; }
 
 #define MCHK(expr, what)                                                                       \
@@ -485,6 +585,19 @@ lbm_status mlp_closure(const float* y, const double* eps, int64_t n, double nu, 
     k_closure<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(y, eps, n, nu, nu_eff, drag);
     MCHK(hipGetLastError(), "closure");
     MCHK(hipStreamSynchronize((hipStream_t)stream), "synchronise");
+    return LBM_OK;
+}
+
+
+lbm_status mlp_profile_loss(const float* y, const double* eps, const double* u_target, int32_t nprof, int32_t nz,
+                            double nu, double G, double weight, float* dy, double* loss, void* stream) {
+    if (!y || !eps || !u_target || !dy || !loss || nprof < 1 || nz < 5 || nz > PL_MAX || !(nu > 0) ||
+        !(weight >= 0))
+        return set_error(LBM_E_INVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    k_profile_loss<<<(unsigned)nprof, 64, 0, st>>>(y, eps, u_target, nz, nu, G, weight / nprof, dy, loss);
+    MCHK(hipGetLastError(), "profile loss");
+    MCHK(hipStreamSynchronize(st), "synchronise");
     return LBM_OK;
 }
 

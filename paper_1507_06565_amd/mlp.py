@@ -16,6 +16,24 @@ NPARAM = 43408
 ROWS = 64
 
 
+def init_params(seed=0):
+    """Initial FP32 parameter vector: normal weights scaled by 1/sqrt(fan-in)
+    (x sqrt(2) before the GELU layers), zero biases, zero padding rows and
+    columns; the last layer starts small so the closure starts near
+    (nu_eff, drag) = (nu, (1 - eps) log 2)."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(NPARAM, np.float32)
+    o = 0
+    for k, n, used_k, used_n, gain in ((64, 128, 33, 128, 2.0), (128, 128, 128, 128, 2.0),
+                                       (128, 128, 128, 128, 2.0), (128, 16, 128, 2, 0.1)):
+        w = np.zeros((k, n), np.float32)
+        w[:used_k, :used_n] = rng.standard_normal((used_k, used_n)) * np.sqrt(gain / used_k)
+        p[o:o + k * n] = w.ravel()
+        o += k * n + n  # weights, then the (zero) biases
+    assert o == NPARAM
+    return p
+
+
 def _p(t):
     return C.c_void_p(t.data_ptr())
 
@@ -87,6 +105,22 @@ class ClosureNet:
         self.backward(x_bf16, dy)
         self.adam(lr)
         return L
+
+    def profile_loss(self, y, eps, u_target, nprof, nz, nu, G, weight=1.0, dy=None):
+        """Loss of nprof profiles through the steady gray column; dL/dy goes
+        to rows [0, nprof*nz) of dy (allocated like y if None).  Returns
+        (per-profile losses as numpy, dy)."""
+        if dy is None:
+            dy = torch.zeros_like(y)
+        e = torch.as_tensor(np.ascontiguousarray(eps, np.float64) if isinstance(eps, np.ndarray) else eps,
+                            dtype=torch.float64, device=self.dev).contiguous()
+        t = torch.as_tensor(np.ascontiguousarray(u_target, np.float64) if isinstance(u_target, np.ndarray)
+                            else u_target, dtype=torch.float64, device=self.dev).contiguous()
+        assert y.shape[0] >= nprof * nz and e.numel() == nprof * nz and t.numel() == nprof * nz
+        loss = torch.empty(nprof, dtype=torch.float64, device=self.dev)
+        check(lib.mlp_profile_loss(_p(y), _p(e), _p(t), nprof, nz, nu, G, weight, _p(dy), _p(loss), self.s),
+              "mlp_profile_loss")
+        return loss.cpu().numpy(), dy
 
     def windows(self, eps_cols):
         """eps_cols: (ncols, nz) FP64 numpy -> BF16 inputs (rows padded to 64)."""

@@ -130,3 +130,30 @@ def test_training_reduces_loss():
         L0 = L if L0 is None else L0
     say("loss", L0, "->", L)
     assert L < 0.05 * L0
+
+
+def test_profile_loss_parity():
+    """Steady-column loss and its adjoint gradient against the FP64
+    reference on the same network outputs (both FP64; tolerance set by the
+    FP32 outputs and the FP32 gradient store)."""
+    from oracle import closure as CL
+    from paper_1507_06565_amd import mlp
+    net, pr, Xr, xb, rng = setup(B=64, seed=5)
+    nprof, nz, nu, G = 3, 48, 1.0 / 6.0, 1e-6
+    eps = rng.uniform(0.4, 1.0, (nprof, nz))
+    eps[:, 30:] = 1.0
+    eps[:, 0] = eps[:, -1] = 0.0
+    ut = np.stack([CL.steady_profile(np.where(e > 0, e, 1.0), np.full(nz, nu), np.where(e < 1, 0.02, 0.0), G)
+                   for e in eps]) * rng.uniform(0.8, 1.2, (nprof, 1))
+    B = 192
+    Y = rng.normal(0, 0.5, (B, 16)).astype(np.float32)
+    y = torch.tensor(Y).cuda()
+    L, dy = net.profile_loss(y, eps.ravel(), ut.ravel(), nprof, nz, nu, G, 0.5)
+    Lr, dYr = CL.profile_loss(Y.astype(np.float64), eps.ravel(), ut.ravel(), nprof, nz, nu, G, 0.5)
+    say("profile loss", L, Lr)
+    assert np.allclose(L, Lr, rtol=1e-10, atol=0)
+    g = dy.cpu().numpy()
+    assert np.all(g[nprof * nz:] == 0)
+    e1 = rel(g[:nprof * nz].astype(np.float64), dYr)
+    say("profile loss gradient rel L2", e1)
+    assert e1 <= 1e-6
