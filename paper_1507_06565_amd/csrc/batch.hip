@@ -38,6 +38,7 @@ struct BatchDom {
     const uint32_t* info;
     const int32_t* segbase;
     const float* lparam;
+    float* pv;        // partial bounce-back values, one per link
     double* partial;  // one FP64 partial sum per 64-cell chunk
     int32_t nx, ny, nz, ncells;
 };
@@ -133,6 +134,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
         const uint32_t* info = uniform_ptr(D->info);
         const int32_t* segbase = uniform_ptr(D->segbase);
         const float* lparam = uniform_ptr(D->lparam);
+        float* pv = uniform_ptr(D->pv);
         double* partial = uniform_ptr(D->partial);
         const int nchunk = (N + 63) >> 6;
         const int64_t s0 = a.steps[d];
@@ -148,11 +150,11 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
                 if (c < N) {
                     const int x = c % nx, t = c / nx, y = t % ny, z = t / ny;
                     if (even)
-                        ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, nullptr, info, segbase, lparam, a.k, nx, ny,
-                                                                  nz, c, x, y, z);
+                        ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, nullptr, info, segbase, lparam, pv, pv,
+                                                                  a.k, nx, ny, nz, c, x, y, z);
                     else
-                        ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, nullptr, info, segbase, lparam, a.k, nx, ny, nz,
-                                                                 c, x, y, z);
+                        ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, nullptr, info, segbase, lparam, pv, pv,
+                                                                 a.k, nx, ny, nz, c, x, y, z);
                 }
                 if (check) {
                     const double w = wave_sum((double)ux);
@@ -214,6 +216,7 @@ int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct DomPlan {
     int64_t N, stride, nl, nchunk, nseed;
+    int64_t grid;  // floats of the state block: Q population arrays + partial values
     int64_t off_pop, off_info, off_segbase, off_lparam, off_partial, off_seed;
 };
 
@@ -273,7 +276,8 @@ lbm_status plan(const std::vector<DomainGeo>& doms, const lbm_params& p, BatchCt
         if (moving)
             for (auto s : G.lsurf)
                 if (s == SURF_WALL_HI) ++P.nseed;
-        P.off_pop = o; o = align_up(o + Q * P.stride * 4, 256);
+        P.grid = Q * P.stride + align_up(P.nl + Q, 64);
+        P.off_pop = o; o = align_up(o + P.grid * 4, 256);
         P.off_info = o; o = align_up(o + P.N * 4, 256);
         P.off_segbase = o; o = align_up(o + ((P.N >> SEG_SHIFT) + 1) * 4, 256);
         P.off_lparam = o; o = align_up(o + (P.nl + Q) * 4, 256);
@@ -315,7 +319,7 @@ lbm_status reset(BatchCtx* b) {
     for (int d = 0; d < b->ndom; ++d) {
         const DomPlan& P = b->plans[d];
         float* pop = reinterpret_cast<float*>(b->buf + P.off_pop);
-        HIPCHK(launch_fill_zero(pop, Q * P.stride, b->stream), "zero populations");
+        HIPCHK(launch_fill_zero(pop, P.grid, b->stream), "zero populations");
         if (P.nseed > 0)
             HIPCHK(launch_scatter(pop, reinterpret_cast<const int64_t*>(b->buf + P.off_seed),
                                   reinterpret_cast<const float*>(b->buf + P.off_seed + P.nseed * 8), P.nseed,
@@ -466,6 +470,7 @@ lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, d
         T.info = reinterpret_cast<const uint32_t*>(buf + P.off_info);
         T.segbase = reinterpret_cast<const int32_t*>(buf + P.off_segbase);
         T.lparam = reinterpret_cast<const float*>(buf + P.off_lparam);
+        T.pv = reinterpret_cast<float*>(buf + P.off_pop) + Q * P.stride;
         T.partial = reinterpret_cast<double*>(buf + P.off_partial);
         T.nx = doms[d].desc.nx; T.ny = doms[d].desc.ny; T.nz = doms[d].desc.nz; T.ncells = (int32_t)P.N;
         hipError_t e = hipMemcpyAsync(buf + P.off_info, im.info.data(), im.info.size() * 4, hipMemcpyHostToDevice, s);
@@ -588,7 +593,7 @@ static const int64_t kBatchMagic = 0x4c424d4241544348;  // "LBMBATCH"
 
 lbm_status batch_state_bytes(BatchCtx* b, int64_t* bytes) {
     int64_t n = 32;
-    for (auto& P : b->plans) n += 24 + Q * P.stride * 4;
+    for (auto& P : b->plans) n += 24 + P.grid * 4;
     *bytes = n;
     return LBM_OK;
 }
@@ -607,8 +612,8 @@ lbm_status batch_save(BatchCtx* b, void* host, int64_t bytes, int64_t steps) {
         std::memcpy(&meta[2], &up[d], 8);
         std::memcpy(o, meta, 24);
         o += 24;
-        HIPCHK(hipMemcpyAsync(o, b->buf + P.off_pop, Q * P.stride * 4, hipMemcpyDeviceToHost, b->stream), "save");
-        o += Q * P.stride * 4;
+        HIPCHK(hipMemcpyAsync(o, b->buf + P.off_pop, P.grid * 4, hipMemcpyDeviceToHost, b->stream), "save");
+        o += P.grid * 4;
     }
     HIPCHK(hipStreamSynchronize(b->stream), "synchronise");
     return LBM_OK;
@@ -628,8 +633,8 @@ lbm_status batch_load(BatchCtx* b, const void* host, int64_t bytes) {
         b->steps[d] = meta[0];
         b->status[d] = (int32_t)meta[1];
         std::memcpy(&up[d], &meta[2], 8);
-        HIPCHK(hipMemcpyAsync(b->buf + P.off_pop, o, Q * P.stride * 4, hipMemcpyHostToDevice, b->stream), "load");
-        o += Q * P.stride * 4;
+        HIPCHK(hipMemcpyAsync(b->buf + P.off_pop, o, P.grid * 4, hipMemcpyHostToDevice, b->stream), "load");
+        o += P.grid * 4;
     }
     HIPCHK(hipMemcpyAsync(b->buf + b->off_steps, b->steps.data(), b->ndom * 8, hipMemcpyHostToDevice, b->stream),
            "load");

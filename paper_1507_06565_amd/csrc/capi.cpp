@@ -67,6 +67,7 @@ lbm_status rates(const lbm_params& p, double& wp, double& wm) {
 // --------------------------------------------------------- memory plan --
 struct Plan {
     int64_t N = 0, stride = 0, nb = 0, nl = 0, np = 0, chunk = 0, nseed = 0;
+    int64_t grid = 0;  // floats per state block: Q population arrays + the partial values
     int64_t off_pop = 0, off_info = 0, off_segbase = 0, off_lparam = 0, off_seed = 0, off_red = 0, off_fields = 0;
     int64_t total = 0;
 };
@@ -91,7 +92,8 @@ Plan plan_single(const DomainGeo& g, const lbm_params& p) {
     P.chunk = std::min<int64_t>(P.N, std::max<int64_t>((int64_t)d.nx * d.ny, 1 << 20));
     int64_t o = 0;
     const int64_t ngrid = (p.layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
-    P.off_pop = o; o = align_up(o + ngrid * Q * P.stride * 4, 256);
+    P.grid = Q * P.stride + align_up(P.nl + Q, 64);
+    P.off_pop = o; o = align_up(o + ngrid * P.grid * 4, 256);
     P.off_info = o; o = align_up(o + P.N * 4, 256);
     P.off_segbase = o; o = align_up(o + ((P.N >> SEG_SHIFT) + 1) * 4, 256);
     P.off_lparam = o; o = align_up(o + (P.nl + Q) * 4, 256);
@@ -143,7 +145,7 @@ namespace {
 
 MomentArgs moment_args(const lbm_ctx* c) {
     MomentArgs m{};
-    m.A = reinterpret_cast<const float*>(c->buf + c->P.off_pop) + (int64_t)c->cur * Q * c->P.stride;
+    m.A = reinterpret_cast<const float*>(c->buf + c->P.off_pop) + (int64_t)c->cur * c->P.grid;
     m.stride = c->P.stride;
     m.info = reinterpret_cast<const uint32_t*>(c->buf + c->P.off_info);
     m.nx = c->d.nx; m.ny = c->d.ny; m.nz = c->d.nz;
@@ -222,8 +224,8 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
         float* base = reinterpret_cast<float*>(c->buf + c->P.off_pop);
         int par = P_EVEN;
         if (c->p.layout == LBM_LAYOUT_TWOGRID) {
-            a.A = base + (int64_t)c->cur * Q * c->P.stride;
-            a.B = base + (int64_t)(1 - c->cur) * Q * c->P.stride;
+            a.A = base + (int64_t)c->cur * c->P.grid;
+            a.B = base + (int64_t)(1 - c->cur) * c->P.grid;
         } else {
             a.A = base;
             a.B = nullptr;
@@ -233,6 +235,8 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
             a.pa[k] = a.A + k * c->P.stride;
             a.pb[k] = a.B ? a.B + k * c->P.stride : nullptr;
         }
+        a.pva = a.A + Q * c->P.stride;
+        a.pvb = a.B ? a.B + Q * c->P.stride : a.pva;
         a.xcd_remap = c->xcd_remap;
         a.nt = c->nt;
         hipError_t e = launch_sweep(a, c->p.layout, par, c->d.bc, c->block, c->stream);
@@ -244,12 +248,12 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
     return LBM_OK;
 }
 
-// rest state: every population zero (f = w rho0), moving-wall partial values
-// seeded
+// rest state: every population and partial value zero (f = w rho0), the
+// moving-wall partial values seeded
 hipError_t reset_state(lbm_ctx* c) {
     const int64_t ngrid = (c->p.layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
     float* pop = reinterpret_cast<float*>(c->buf + c->P.off_pop);
-    hipError_t e = launch_fill_zero(pop, ngrid * Q * c->P.stride, c->stream);
+    hipError_t e = launch_fill_zero(pop, ngrid * c->P.grid, c->stream);
     if (e == hipSuccess && c->P.nseed > 0)
         e = launch_scatter(pop, reinterpret_cast<const int64_t*>(c->buf + c->P.off_seed),
                            reinterpret_cast<const float*>(c->buf + c->P.off_seed + c->P.nseed * 8), c->P.nseed,
@@ -549,14 +553,14 @@ lbm_status lbm_totals(lbm_ctx* c, int32_t dom, double* mass, double momentum[3])
     return LBM_OK;
 }
 
-// checkpoint image: 4 int64 header {magic, steps, parity, cur} + populations
-// of the current grid (the partial bounce-back values live in them)
+// checkpoint image: 4 int64 header {magic, steps, parity, cur} + the current
+// state block (populations and partial bounce-back values)
 static const int64_t kMagic = 0x4c424d53544154;  // "LBMSTAT"
 
 lbm_status lbm_state_bytes(lbm_ctx* c, int64_t* bytes) {
     if (!c || !bytes) return fail(LBM_E_INVAL, "bad arguments");
     if (c->batch) return batch_state_bytes(c->batch, bytes);
-    *bytes = 32 + Q * c->P.stride * 4;
+    *bytes = 32 + c->P.grid * 4;
     return LBM_OK;
 }
 
@@ -569,8 +573,8 @@ lbm_status lbm_save(lbm_ctx* c, void* host_buf, int64_t bytes) {
     int64_t* h = reinterpret_cast<int64_t*>(host_buf);
     h[0] = kMagic; h[1] = c->steps; h[2] = c->parity; h[3] = 0;
     char* dst = reinterpret_cast<char*>(host_buf) + 32;
-    const char* pop = c->buf + c->P.off_pop + (int64_t)c->cur * Q * c->P.stride * 4;
-    HIP_TRY(hipMemcpyAsync(dst, pop, Q * c->P.stride * 4, hipMemcpyDeviceToHost, c->stream), "save populations");
+    const char* pop = c->buf + c->P.off_pop + (int64_t)c->cur * c->P.grid * 4;
+    HIP_TRY(hipMemcpyAsync(dst, pop, c->P.grid * 4, hipMemcpyDeviceToHost, c->stream), "save populations");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
     return LBM_OK;
 }
@@ -589,7 +593,7 @@ lbm_status lbm_load(lbm_ctx* c, const void* host_buf, int64_t bytes) {
     if (h[0] != kMagic) return fail(LBM_E_INVAL, "not a state image");
     const char* src = reinterpret_cast<const char*>(host_buf) + 32;
     c->cur = 0;
-    HIP_TRY(hipMemcpyAsync(c->buf + c->P.off_pop, src, Q * c->P.stride * 4, hipMemcpyHostToDevice, c->stream),
+    HIP_TRY(hipMemcpyAsync(c->buf + c->P.off_pop, src, c->P.grid * 4, hipMemcpyHostToDevice, c->stream),
             "load populations");
     HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
     c->steps = h[1];

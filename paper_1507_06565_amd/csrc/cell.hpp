@@ -13,19 +13,18 @@
 //     g_k(x, t+1) = c1 gt_kk(x) + c0 gt_kk(x - e_kk) + cb gt_k(x) [+ wall]
 // (eq. (noslip), eq. (CLI), or Bouzidi), gt being post-collision values of
 // step t.  At the end of step t the cell itself owns gt_kk(x) and gt_k(x), so
-// it stores the partial value P = c1 gt_kk(x) + cb gt_k(x) [+ wall] straight
-// into the slot it will pull direction k from at step t+1 -- a slot that
-// would otherwise stream out of the solid and that no other cell reads or
-// writes:
-//   two-grid   : destination grid, solid neighbour's slot B[k][x + e_kk]
-//   AA, even   : A[kk][x + e_kk]   (the odd step pulls k from there)
-//   AA, odd    : A[k][x]           (the even step pulls k from there)
-// At step t+1 the plain pull returns P and the cell adds c0 gt_kk(x - e_kk),
-// which is the value it pulls for direction kk.  The only per-link data read
-// is the link coefficient; c0 = 0 (simple bounce-back, moving wall, a second
-// node that is not fluid, Bouzidi with q >= 1/2) needs nothing at all at the
-// start of the step.  Arithmetic is identical in every layout, so the
-// layouts agree bit for bit.
+// it stores the partial value P = c1 gt_kk(x) + cb gt_k(x) [+ wall] in a
+// per-link buffer (one float per link, in link order, so the values of a
+// wavefront's cells are contiguous); at step t+1 the cell reads P back and
+// adds c0 gt_kk(x - e_kk), which is the value it pulls for direction kk.
+// The per-link data read is the link coefficient and P.  Each link's P is
+// read and written by its own cell only.
+//
+// Solid cells are not updated, but a solid cell whose 32-cell group (one
+// 128-byte line of every population array) contains fluid cells stores zeros
+// into its own slots, so that the group's stores cover whole lines: partial
+// lines cost extra HBM cycles.  No cell reads a solid cell's slots (the pull
+// of a link direction is replaced by P), so the zeros are never used.
 //
 // AA state locations: after an even step gt_k(x) is stored at A[kbar][x];
 // after an odd step at A[k][x + e_k].  An even step reads A[k][x] and writes
@@ -146,8 +145,9 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD>
 __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb, const uint32_t* __restrict__ info,
                                              const int32_t* __restrict__ segbase,
-                                             const float* __restrict__ lparam, const CellConsts& K, int nx,
-                                             int ny, int nz, int c, int x, int y, int z) {
+                                             const float* __restrict__ lparam, const float* pva, float* pvb,
+                                             const CellConsts& K, int nx, int ny, int nz, int c, int x, int y,
+                                             int z) {
 #pragma clang fp contract(off)
     const unsigned X[3] = {(unsigned)(x == 0 ? nx - 1 : x - 1), (unsigned)x, (unsigned)(x == nx - 1 ? 0 : x + 1)};
     const unsigned Y[3] = {(unsigned)(y == 0 ? ny - 1 : y - 1), (unsigned)y, (unsigned)(y == ny - 1 ? 0 : y + 1)};
@@ -180,33 +180,44 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) asm volatile("" ::"v"(g[k]));
-    if (inf == CELL_SOLID_WORD) return 0.0f;
-    const uint32_t mask = inf & LINK_MASK_BITS;
+    // a solid cell whose 32-cell group holds fluid runs along with the fluid
+    // lanes and stores zeros in the same store instructions (see above)
+    const bool solid = inf == CELL_SOLID_WORD;
+    const uint64_t fluid_lanes = __ballot(!solid);
+    if (solid) {
+        const uint32_t grp = (__lane_id() & 32) ? (uint32_t)(fluid_lanes >> 32) : (uint32_t)fluid_lanes;
+        if (grp == 0u) return 0.0f;
+    }
+    const uint32_t mask = solid ? 0u : (inf & LINK_MASK_BITS);
 
-    // 2) links: the pulled value of an unknown population is the partial
-    //    value P stored last step; add c0 times the second node's value
+    // 2) links: the unknown population is the partial value P stored last
+    //    step plus c0 times the second node's value
     float prm[Q];
     if (mask) {
         const int base = segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
-        // every coefficient load is issued before any is used, without
-        // branches: for a direction that is not a link the rank points at a
-        // neighbouring record (the array is padded), whose value is unused
+        // every coefficient and partial-value load is issued before any is
+        // used, without branches: for a direction that is not a link the
+        // rank points at a neighbouring record (the arrays are padded), whose
+        // value is unused
         const __attribute__((address_space(1))) char* lp = (const __attribute__((address_space(1))) char*)lparam;
+        const __attribute__((address_space(1))) char* vp = (const __attribute__((address_space(1))) char*)pva;
+        float pv[Q];
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int kk = opp(k);
             const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
             prm[k] = *(const __attribute__((address_space(1))) float*)(lp + (li << 2));
+            pv[k] = *(const __attribute__((address_space(1))) float*)(vp + (li << 2));
         }
-        // in place: g[kk] is read only when (x, k) is not itself a link, so
-        // it still holds its pulled value
+        // in place: g[kk] is read only when c0 != 0, i.e. when x + e_k is
+        // fluid, so (x, k) is not itself a link and g[kk] is its pulled value
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int kk = opp(k);
             if (mask & (1u << (kk - 1))) {
                 float c1, c0, cb;
                 bb_coeffs<BC>(prm[k], c1, c0, cb);
-                if (c0 != 0.0f) g[k] += c0 * g[kk];
+                g[k] = (c0 != 0.0f) ? pv[k] + c0 * g[kk] : pv[k];
             }
         }
     }
@@ -218,12 +229,13 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
     float* const* D = (LAYOUT == L_TWOGRID) ? pb : pa;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
+        const float v = solid ? 0.0f : g[k];
         if (LAYOUT == L_TWOGRID)
-            st<NT>(&AT(D, k, uc), g[k]);
+            st<NT>(&AT(D, k, uc), v);
         else if (PARITY == P_EVEN)
-            st<NT>(&AT(D, opp(k), uc), g[k]);
+            st<NT>(&AT(D, opp(k), uc), v);
         else
-            AT(D, k, NB(L::ex[k], L::ey[k], L::ez[k])) = g[k];
+            AT(D, k, NB(L::ex[k], L::ey[k], L::ez[k])) = v;
     }
     // 5) partial bounce-back values for the next step; with RELOAD the
     //    coefficients are read again (a cache hit) rather than held in
@@ -237,22 +249,18 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
             if (mask & (1u << (kk - 1))) {
                 float pk = prm[k];
                 if (RELOAD) {
-                    const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
-                    pk = __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)(lp + (li << 2)));
+                    const uint32_t lr = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
+                    pk = __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)(lp + (lr << 2)));
                 }
                 float c1, c0, cb;
                 bb_coeffs<BC>(pk, c1, c0, cb);
                 const float P = c1 * g[kk] + cb * g[k] + (pk != pk ? K.wterm[k] : 0.0f);
-                if (LAYOUT == L_TWOGRID)
-                    AT(D, k, NB(L::ex[kk], L::ey[kk], L::ez[kk])) = P;
-                else if (PARITY == P_EVEN)
-                    AT(D, kk, NB(L::ex[kk], L::ey[kk], L::ez[kk])) = P;
-                else
-                    AT(D, k, uc) = P;
+                const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
+                *(__attribute__((address_space(1))) float*)((__attribute__((address_space(1))) char*)pvb + (li << 2)) = P;
             }
         }
     }
-    return ux;
+    return solid ? 0.0f : ux;
 #undef NB
 }
 

@@ -8,7 +8,7 @@
 
 namespace lbm {
 
-lbm_status build_images(const DomainGeo& G, int layout, int64_t stride, const CellConsts& K, DeviceImages& im,
+lbm_status build_images(const DomainGeo& G, int /*layout*/, int64_t stride, const CellConsts& K, DeviceImages& im,
                         std::string& err) {
     const int64_t N = G.ncells();
     const int64_t nl = (int64_t)G.lcell.size();
@@ -59,16 +59,11 @@ lbm_status build_images(const DomainGeo& G, int layout, int64_t stride, const Ce
         }
         im.lparam[i] = prm;
         if (mw) {
-            // moving-wall links start from the wall term alone: seed the slot
-            // the first step pulls the unknown population k = opp(kk) from
-            const int k = opp(kk);
-            const int xs = (x + D3Q19::ex[kk] + nx) % nx, ys = (y + D3Q19::ey[kk] + ny) % ny,
-                      zs = (z + D3Q19::ez[kk] + nz) % nz;
-            const int64_t solid = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
-            // two-grid pulls k from the solid neighbour's slot; AA (first step
-            // even) from the cell's own slot
-            im.seed_idx.push_back((int64_t)k * stride + (layout == LBM_LAYOUT_TWOGRID ? solid : cell));
-            im.seed_val.push_back(K.wterm[k]);
+            // moving-wall links start from the wall term alone: the partial
+            // value that the first step reads (state block 0, after the Q
+            // population arrays)
+            im.seed_idx.push_back((int64_t)Q * stride + i);
+            im.seed_val.push_back(K.wterm[opp(kk)]);
         }
     }
     return LBM_OK;

@@ -76,6 +76,8 @@ struct SweepArgs {
     const int32_t* segbase;
     const float* lparam;  // CLI: kappa; Bouzidi: q; NaN: moving-wall bounce-back;
                           // padded with Q entries so that rank lookups stay in bounds
+    float* pva;           // partial bounce-back values read this step (one per link)
+    float* pvb;           // ... and written for the next step (AA: pva == pvb)
     int32_t nx, ny, nz, ncells;
     CellConsts k;
     int32_t xcd_remap;
