@@ -32,8 +32,9 @@ def log(*a):
 def algorithmic_bytes(n_fluid, n_cells, n_links):
     """Minimal HBM bytes of one sweep step: 19 FP32 loads + 19 FP32 stores per
     fluid cell, the 4 B cell word of every cell and, per boundary link, its
-    4 B coefficient read and the 4 B partial bounce-back value stored."""
-    return 152 * n_fluid + 4 * n_cells + 8 * n_links
+    4 B coefficient and the 4 B partial bounce-back value read and the new
+    partial value stored (12 B)."""
+    return 152 * n_fluid + 4 * n_cells + 12 * n_links
 
 
 def sampled_window_check(dom, params, ctx_factory, geo, nsteps=8, nwin=12, seed=0):
