@@ -12,6 +12,10 @@ Prints ONE JSON line (rank 0) with MLUPS as `value`, plus the roofline of the
 sweep kernel and the CPU oracle's rate on a bounded sample of the workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-check]
+    python bench.py --workload rev-batch [--samples 512] [--out profiles.json]
+
+The second form times the batched REV workload (512 periodic cubes to steady
+state in persistent launches) and reports its aggregate MLUPS instead.
 """
 import argparse
 import json
@@ -93,6 +97,140 @@ def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0):
                       f"{nsteps} steps, FP64 two-grid, {dt:.1f} s"}
 
 
+def _gen_rev(i):
+    from paper_1507_06565_amd import workloads as W
+    d, p, target, eps = W.rev_sample_c3(i)
+    return i, d, p, target, eps
+
+
+def rev_batch(args):
+    """512 periodic REV cubes (edge in {32,48,64,96}, porosity U[0.35,0.9],
+    radii U[3,10]) in one batched persistent launch per chunk of steps, to
+    steady state; the launch shape is autotuned once and the team size grows
+    as samples converge (every shape gives the same result bit for bit)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    n = args.samples
+    t0 = time.perf_counter()
+    # sphere packings on the host, before the GPU is touched
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        gen = sorted(pool.map(_gen_rev, range(n), chunksize=4), key=lambda r: r[0])
+    doms = [g[1] for g in gen]
+    params = gen[0][2]
+    log(f"{n} REV samples generated ({time.perf_counter() - t0:.1f} s); edges "
+        f"{dict(zip(*np.unique([d.nx for d in doms], return_counts=True)))}")
+
+    import torch
+
+    from paper_1507_06565_amd import lbm
+
+    t0 = time.perf_counter()
+    geo = lbm.Geometry(doms)
+    info = np.array([geo.info(i)[1:] for i in range(n)], dtype=np.int64)  # fluid, links
+    cells = np.array([d.nx * d.ny * d.nz for d in doms], dtype=np.int64)
+    log(f"geometry: {cells.sum()} cells, {info[:, 0].sum()} fluid, {info[:, 1].sum()} links "
+        f"({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.set_device(0)
+    ctx = lbm.Context(geo, params)
+    block, W0 = ctx.autotune(10) if not args.no_autotune else ctx.batch_get_launch()
+    log(f"autotuned batched launch (block, workgroups per sample): ({block}, {W0})")
+    resident = 256 * 1024 // block  # workgroups of this size resident on 256 CUs at 4 waves per SIMD
+    chunk = args.chunk
+    prev = np.zeros(n, dtype=np.int64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W = W0
+    while True:
+        steps = ctx.run_to_steady(1e-7, 100, chunk)
+        adv = steps - prev
+        prev = steps
+        running = int((adv == chunk).sum())
+        log(f"  {time.perf_counter() - t0:7.1f} s: {n - running} of {n} samples steady, "
+            f"steps up to {int(steps.max())}, team size {W}")
+        if running == 0 or steps.max() >= args.max_steps:
+            break
+        # fewer samples left: give each more workgroups (next power of two
+        # of resident workgroups per running sample)
+        want = 1 << max(0, int(np.ceil(np.log2(max(1.0, resident / running)))))
+        Wn = int(min(64, max(W0, want)))
+        if Wn != W:
+            W = Wn
+            ctx.batch_set_launch(block, W)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps = prev
+    converged = int((steps < args.max_steps).sum())
+    updates = int((cells * steps).sum())
+    alg = float(((152 * info[:, 0] + 4 * cells + 12 * info[:, 1]) * steps).sum())
+    mlups = updates / wall / 1e6
+    K = np.array([ctx.permeability(dom=i) for i in range(n)])
+    eps = np.array([g[4] for g in gen])
+    log(f"batch: {wall:.1f} s, {updates / 1e9:.1f} G cell updates, {mlups:.0f} MLUPS, "
+        f"{alg / wall / 1e9:.0f} GB/s algorithmic")
+    if args.out:
+        prof = []
+        for i in range(n):
+            sup, _, por = ctx.average_profile(dom=i)
+            prof.append({"edge": doms[i].nx, "porosity": float(eps[i]), "K": float(K[i]), "steps": int(steps[i]),
+                         "eps_z": por.tolist(), "u_z": sup.tolist()})
+        with open(args.out, "w") as f:
+            json.dump(prof, f)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = rev_cpu_baseline(doms, params)
+        log("cpu baseline:", cpu)
+    out = {
+        "metric": "MLUPS + HBM GB/s (% peak) at stated FP32 error; closure vs pore-scale speed/err",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": int(steps.max()),
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n} periodic REV cubes, edge in {{32,48,64,96}}, porosity U[0.35,0.9], radii "
+                               f"U[3,10], TRT Lambda 3/16 tau 1.0, force 1e-6, CLI, AA, FP32 shifted, to steady "
+                               f"state (relative change <= 1e-7 per 100 steps)",
+                   "samples": n, "cells": int(cells.sum()), "fluid_cells": int(info[:, 0].sum()),
+                   "links": int(info[:, 1].sum()), "block": block, "workgroups_per_sample": W0},
+        "batch": {"wall_s": round(wall, 2), "converged": converged, "cell_updates": updates,
+                  "steps_min": int(steps.min()), "steps_median": int(np.median(steps)),
+                  "steps_max": int(steps.max()), "K_min": float(K.min()), "K_max": float(K.max())},
+        "effective_gbs": round(alg / wall / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": round(alg / wall / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / wall / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_total": alg},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def rev_cpu_baseline(doms, params, budget_s=15.0):
+    """The FP64 oracle, as it is, on one 48^3 sample of the batch."""
+    import oracle
+
+    d = next(x for x in doms if x.nx == 48)
+    sim = oracle.Sim(d, params)
+    sim.step(1)
+    t = time.perf_counter()
+    sim.step(20)
+    t1 = (time.perf_counter() - t) / 20
+    nsteps = int(max(1, min(100000, budget_s / max(t1, 1e-6))))
+    t = time.perf_counter()
+    sim.step(nsteps)
+    dt = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": d.nx ** 3 * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"one 48^3 REV cube of the batch ({d.name}), {nsteps} steps, FP64 two-grid, {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,11 +241,20 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counter scaling)")
+    ap.add_argument("--workload", choices=("bed", "rev-batch"), default="bed",
+                    help="bed: the large coupled domain (default); rev-batch: the batched REV cubes")
+    ap.add_argument("--samples", type=int, default=512, help="rev-batch: number of cubes")
+    ap.add_argument("--chunk", type=int, default=2000, help="rev-batch: steps per persistent launch")
+    ap.add_argument("--max-steps", type=int, default=2_000_000, help="rev-batch: cap per sample")
+    ap.add_argument("--out", default=None, help="rev-batch: write per-sample K and profiles (JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the z-slab decomposition is described in the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "rev-batch":
+        rev_batch(args)
+        return
 
     import numpy as np
     import torch

@@ -49,7 +49,7 @@ struct BatchArgs {
     const int32_t* order;  // queue: domains sorted largest first
     int32_t* queue;        // next queue position
     uint32_t* bar;         // barrier counter per team
-    int32_t* slot;         // per team: {domain, stop flag}
+    int32_t* slot;         // per team: {domain of even pops, domain of odd pops, stop flag, unused}
     int64_t* steps;        // per domain: steps run so far
     double* uprev;         // per domain: last checked sum of u_x
     int32_t* status;       // per domain: 0 running, 1 converged, -1 unstable
@@ -112,14 +112,19 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
     const int W = a.W;
     const int team = blockIdx.x / W, rank = blockIdx.x % W;
     uint32_t gen = 0;
-    for (;;) {
+    // The popped domain alternates between two slots: a domain that needs no
+    // step (already steady) passes no barrier before the next pop, so a
+    // single slot could be overwritten before a slow team member has read it.
+    // The next write to the same slot needs the next pop's barrier, which
+    // every member reaches only after reading.
+    for (uint32_t npop = 0;; ++npop) {
+        int32_t* dslot = &a.slot[4 * team + (npop & 1)];
         if (rank == 0 && threadIdx.x == 0) {
             const int q = atomicAdd(a.queue, 1);
-            __hip_atomic_store(&a.slot[2 * team], q < a.ndom ? a.order[q] : -1, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(dslot, q < a.ndom ? a.order[q] : -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (!team_barrier(a, team, ++gen * (uint32_t)W, &s_ok)) return;
-        if (threadIdx.x == 0) s_dom = load_acq(&a.slot[2 * team]);
+        if (threadIdx.x == 0) s_dom = load_acq(dslot);
         __syncthreads();
         // uniform across the workgroup: keep it (and everything derived from
         // it, like the 19 population bases) in scalar registers
@@ -177,11 +182,11 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
                         if (!(fabs(U) < 0.4 * (double)N)) st = -1;  // NaN or runaway velocity
                         else if (fabs(U - Up) <= a.tol * fabs(U)) st = 1;
                         a.uprev[d] = U;
-                        __hip_atomic_store(&a.slot[2 * team + 1], st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&a.slot[4 * team + 2], st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
                 if (!team_barrier(a, team, ++gen * (uint32_t)W, &s_ok)) return;
-                if (threadIdx.x == 0) s_stop = load_acq(&a.slot[2 * team + 1]);
+                if (threadIdx.x == 0) s_stop = load_acq(&a.slot[4 * team + 2]);
                 __syncthreads();
                 if (s_stop != 0) {
                     stop = true;
@@ -294,7 +299,7 @@ lbm_status plan(const std::vector<DomainGeo>& doms, const lbm_params& p, BatchCt
     b.off_order = o; o = align_up(o + nd * 4, 256);
     b.off_queue = o; o = align_up(o + 4, 256);
     b.off_bar = o; o = align_up(o + b.max_teams * 4, 256);
-    b.off_slot = o; o = align_up(o + b.max_teams * 8, 256);
+    b.off_slot = o; o = align_up(o + b.max_teams * 16, 256);
     b.off_steps = o; o = align_up(o + nd * 8, 256);
     b.off_uprev = o; o = align_up(o + nd * 8, 256);
     b.off_status = o; o = align_up(o + nd * 4, 256);

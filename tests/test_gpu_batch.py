@@ -130,3 +130,58 @@ def test_batch_restart_bitwise():
     b.step(10)
     for i in range(3):
         assert np.array_equal(a.fields(i)[1], b.fields(i)[1])
+
+
+def test_rev_workload_samples_permeability():
+    """Two cubes of the batched REV workload (edge 32, radii U[3,10]) run to
+    steady state in one batched launch; K against the oracle run to its own
+    steady state within 1e-4."""
+    say("test_rev_workload_samples_permeability")
+    lbm = _lbm()
+    picks = [0, 7]  # the edge-32 samples among the first indices (porosity 0.69 and 0.80)
+    gen = [W.rev_sample_c3(i) for i in picks]
+    doms = [g[0] for g in gen]
+    params = gen[0][1]
+    assert all(d.nx == 32 for d in doms)
+    p = W.Params(**{**params.__dict__, "layout": "aa"})
+    ctx = lbm.Context(lbm.Geometry(doms), p)
+    steps = ctx.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=200000)
+    say("steps", steps)
+    nu = (params.tau_plus - 0.5) / 3.0
+    for i, d in enumerate(doms):
+        k = ctx.permeability(i, 0)
+        ref = oracle.Sim(d, params)
+        prev = None
+        for _ in range(3000):
+            ref.step(100)
+            U = ref.velocity()[0][ref.fluid()].sum()
+            if prev is not None and abs(U - prev) <= 1e-10 * abs(U):
+                break
+            prev = U
+        sup, _, _ = oracle.plane_profile(ref.velocity(), ref.fluid(), 2, 0)
+        kref = oracle.permeability(sup, 0, d.nz, nu, 1.0, params.force[0])
+        say("sample", picks[i], "K", k, "oracle", kref)
+        assert abs(k / kref - 1) <= 1e-4
+
+
+def test_batch_steady_in_chunks_matches_one_call():
+    """run_to_steady in short launches (samples that converged earlier are
+    skipped by the later launches) ends exactly where one long launch ends:
+    same steps per sample, same fields bit for bit."""
+    say("test_batch_steady_in_chunks_matches_one_call")
+    lbm = _lbm()
+    doms = batch_domains()
+    one = lbm.Context(lbm.Geometry(doms), PARAMS)
+    s1 = one.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=200000)
+    chunked = lbm.Context(lbm.Geometry(doms), PARAMS)
+    prev = np.zeros(len(doms), np.int64)
+    for _ in range(2000):
+        s2 = chunked.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=300)
+        adv = s2 - prev
+        prev = s2
+        if np.all(adv < 300):
+            break
+    say("steps", s1, s2)
+    assert np.array_equal(s1, s2)
+    for i in range(len(doms)):
+        assert np.array_equal(one.fields(i)[1], chunked.fields(i)[1]), i
