@@ -258,3 +258,27 @@ def test_c2_full_size_sampled_windows():
     say("C2 sampled cells", checked, "rel L2", e)
     assert checked > 1000
     assert e <= REL_L2
+
+
+def test_c1_20000_steps_against_stored_oracle():
+    """The coupled bed (Bouzidi) over its full 20000 steps in FP32 against the
+    FP64 oracle's state stored by tests/golden/make_c1_drift.py: 4096 sampled
+    fluid cells and the plane-averaged superficial profile."""
+    import json
+    import os
+    say("test_c1_20000_steps_against_stored_oracle")
+    lbm = _lbm()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_20000.json")) as f:
+        gold = json.load(f)
+    d, p, eps = W.coupled_c1()
+    assert abs(eps - gold["bed_porosity"]) == 0
+    ctx = lbm.Context(lbm.Geometry(d), p)
+    ctx.step(gold["steps"])
+    _, u = ctx.fields()
+    got = u.reshape(3, -1)[:, np.array(gold["cells"])].T
+    ref = np.array(gold["u"])
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    sup, _, _ = ctx.average_profile(0, 2, 0)
+    ep = float(np.linalg.norm(sup - np.array(gold["u_sup"])) / np.linalg.norm(gold["u_sup"]))
+    say("C1 20000 steps: sampled cells rel L2", e, "profile rel L2", ep)
+    assert e <= REL_L2 and ep <= REL_L2
