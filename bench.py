@@ -231,6 +231,77 @@ def rev_cpu_baseline(doms, params, budget_s=15.0):
             "sample": f"one 48^3 REV cube of the batch ({d.name}), {nsteps} steps, FP64 two-grid, {dt:.1f} s"}
 
 
+def closure_kernels(args):
+    """Speed of the learned-closure kernels: BF16 MFMA forward and backward of
+    the closure network on B rows, the closure map, and the gray column (one
+    1x1x512 column of the smoothed-step workload to steady state, and 4096
+    columns for a fixed number of steps)."""
+    import numpy as np
+    import torch
+
+    from paper_1507_06565_amd import gray, mlp, workloads as W
+
+    torch.cuda.set_device(0)
+    B = 1 << 16
+    net = mlp.ClosureNet(mlp.init_params(0))
+    rng = np.random.default_rng(0)
+    X = np.zeros((B, 64), np.float32)
+    X[:, :33] = rng.uniform(0.35, 1.0, (B, 33))
+    x = torch.tensor(X).to(torch.bfloat16).cuda()
+    dy = torch.tensor(rng.normal(0, 1e-3, (B, 16)).astype(np.float32)).cuda()
+    s = net.stream
+
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    used = 2 * (33 * 128 + 128 * 128 * 2 + 128 * 2)  # multiply-adds x 2 of the weights in use, per row
+    padded = 2 * (64 * 128 + 128 * 128 * 2 + 128 * 16)  # what the 16x16x32 tiles execute
+    t_inf = timed(lambda: net.forward(x))
+    t_fwd = timed(lambda: net.forward(x, train=True))
+    t_bwd = timed(lambda: net.backward(x, dy))
+    res = {"mlp_rows": B,
+           "forward_ms": round(t_inf, 4), "forward_tflops_used": round(used * B / t_inf / 1e9, 2),
+           "forward_tflops_executed": round(padded * B / t_inf / 1e9, 2),
+           "train_forward_ms": round(t_fwd, 4), "backward_ms": round(t_bwd, 4),
+           "backward_tflops_used": round(2 * used * B / t_bwd / 1e9, 2)}
+    log("mlp:", res)
+    eps, _, _ = W.smoothed_step_porosity(512, 0)
+    nu = 1.0 / 6.0
+    col = gray.GrayColumns(eps, nu / eps, np.where(eps < 1, eps * nu / 2.0, 0.0), G=(1e-6, 0, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = int(col.run_to_steady(1e-7, 100, 2_000_000)[0])
+    dt = time.perf_counter() - t0
+    res.update({"gray_column_nz": 512, "gray_steps_to_steady": steps, "gray_seconds": round(dt, 4),
+                "gray_us_per_step": round(dt / steps * 1e6, 3)})
+    ncol = 4096
+    cols = gray.GrayColumns(np.tile(eps, (ncol, 1)), np.tile(nu / eps, (ncol, 1)),
+                            np.tile(np.where(eps < 1, eps * nu / 2.0, 0.0), (ncol, 1)), G=(1e-6, 0, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cols.run(10000)
+    dt = time.perf_counter() - t0
+    res.update({"gray_columns": ncol, "gray_cell_updates_per_s": round(ncol * 512 * 10000 / dt / 1e9, 2)})
+    log("gray:", res)
+    out = {"metric": "closure kernels: MLP TFLOP/s (BF16 MFMA) and gray-column steps/s", "value": res["forward_tflops_used"],
+           "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "closure network 33-128-128-128-2 on 65536 windows; gray column 1x1x512"},
+           "detail": res,
+           "roofline": {"bound": "mfma", "achieved": res["forward_tflops_executed"], "peak": 2500.0,
+                        "unit": "TFLOP/s", "frac": round(res["forward_tflops_executed"] / 2500.0, 5),
+                        "traffic": None}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,8 +312,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("bed", "rev-batch"), default="bed",
-                    help="bed: the large coupled domain (default); rev-batch: the batched REV cubes")
+    ap.add_argument("--workload", choices=("bed", "rev-batch", "closure-kernels"), default="bed",
+                    help="bed: the large coupled domain (default); rev-batch: the batched REV cubes; "
+                         "closure-kernels: closure network and gray column speed")
     ap.add_argument("--samples", type=int, default=512, help="rev-batch: number of cubes")
     ap.add_argument("--chunk", type=int, default=2000, help="rev-batch: steps per persistent launch")
     ap.add_argument("--max-steps", type=int, default=2_000_000, help="rev-batch: cap per sample")
@@ -254,6 +326,9 @@ def main():
         sys.exit(2)
     if args.workload == "rev-batch":
         rev_batch(args)
+        return
+    if args.workload == "closure-kernels":
+        closure_kernels(args)
         return
 
     import numpy as np
