@@ -143,9 +143,10 @@ void lbm_geometry_free(lbm_geometry* g);
 
 /* ----------------------------------------------------------- pore-scale run --
  * lbm_required_bytes: size of the device buffer lbm_init needs for geometry g
- * and params p (populations, cell info, link records, reduction scratch).
- * With more than one domain the batched layout is used (each domain has its
- * own two-grid state; params.layout is ignored). */
+ * and params p (populations, one partial bounce-back value per link, cell
+ * info, link coefficients, reduction scratch).  With more than one domain the
+ * batched layout is used (each domain has its own AA state; params.layout is
+ * ignored). */
 lbm_status lbm_required_bytes(const lbm_geometry* g, const lbm_params* p, int64_t* bytes);
 
 /* lbm_init: bind a context to the caller's device buffer dev_buf (at least
@@ -198,7 +199,8 @@ lbm_status lbm_fields(lbm_ctx* ctx, int32_t dom, double* host_rho, double* host_
 lbm_status lbm_totals(lbm_ctx* ctx, int32_t dom, double* mass, double momentum[3]);
 
 /* Checkpoint: lbm_state_bytes gives the size of the host image; lbm_save
- * copies populations, step counter and layout parity to host_buf; lbm_load
+ * copies populations, partial bounce-back values, step counter and layout
+ * parity to host_buf; lbm_load
  * restores them into a context built from the same geometry and params.
  * Synchronises.  Restarting from a saved image is bit-identical. */
 lbm_status lbm_state_bytes(lbm_ctx* ctx, int64_t* bytes);

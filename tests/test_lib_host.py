@@ -100,3 +100,21 @@ def test_required_bytes_layouts():
     nl = g.info()[2]
     # the AA layout drops one population grid and adds one float per link
     assert two - aa >= 19 * 4 * 64 * 32 * 40 - 4 * nl - 4096
+
+
+def test_closure_and_gray_argument_validation():
+    """Size and pointer checks of the gray and network entry points, which
+    return before any device work."""
+    from paper_1507_06565_amd._lib import lib
+    E_INVAL = -1
+    n = C.c_int64(0)
+    assert lib.gray_required_bytes(1, 705, C.byref(n)) == E_INVAL
+    assert lib.gray_required_bytes(1, 2, C.byref(n)) == E_INVAL
+    assert lib.gray_required_bytes(0, 64, C.byref(n)) == E_INVAL
+    assert lib.gray_required_bytes(3, 512, C.byref(n)) == 0 and n.value >= 3 * 19 * 512 * 4
+    assert lib.mlp_workspace_bytes(100, C.byref(n)) == E_INVAL
+    assert lib.mlp_workspace_bytes(0, C.byref(n)) == E_INVAL
+    assert lib.mlp_workspace_bytes(128, C.byref(n)) == 0 and n.value > 0
+    # null pointers and sizes out of range are rejected up front
+    assert lib.mlp_profile_loss(None, None, None, 1, 64, 0.1, 1e-6, 1.0, None, None, None) == E_INVAL
+    assert lib.mlp_closure(None, None, 10, 0.1, None, None, None) == E_INVAL
