@@ -86,7 +86,7 @@ def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0):
     t = time.perf_counter()
     sim.step(1)
     t1 = time.perf_counter() - t
-    nsteps = int(max(1, min(50, budget_s / max(t1, 1e-3))))
+    nsteps = int(max(1, min(400, budget_s / max(t1, 1e-3))))
     t = time.perf_counter()
     sim.step(nsteps)
     dt = time.perf_counter() - t
