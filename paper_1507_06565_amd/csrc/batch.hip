@@ -35,6 +35,7 @@ namespace lbm {
 
 struct BatchDom {
     float* pa[Q];
+    uint32_t stride;  // floats between population arrays
     const uint32_t* info;
     const int32_t* segbase;
     const float* lparam;
@@ -133,9 +134,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
         const BatchDom* D = a.doms + d;
         const int N = __builtin_amdgcn_readfirstlane(D->ncells), nx = __builtin_amdgcn_readfirstlane(D->nx),
                   ny = __builtin_amdgcn_readfirstlane(D->ny), nz = __builtin_amdgcn_readfirstlane(D->nz);
-        float* pa[Q];
-#pragma unroll
-        for (int k = 0; k < Q; ++k) pa[k] = uniform_ptr(D->pa[k]);
+        const PopStrided pa{uniform_ptr(D->pa[0]), (uint32_t)__builtin_amdgcn_readfirstlane((int)D->stride)};
         const uint32_t* info = uniform_ptr(D->info);
         const int32_t* segbase = uniform_ptr(D->segbase);
         const float* lparam = uniform_ptr(D->lparam);
@@ -155,10 +154,10 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
                 if (c < N) {
                     const int x = c % nx, t = c / nx, y = t % ny, z = t / ny;
                     if (even)
-                        ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, nullptr, info, segbase, lparam, pv, pv,
+                        ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, pa, info, segbase, lparam, pv, pv,
                                                                   a.k, nx, ny, nz, c, x, y, z);
                     else
-                        ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, nullptr, info, segbase, lparam, pv, pv,
+                        ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, pa, info, segbase, lparam, pv, pv,
                                                                  a.k, nx, ny, nz, c, x, y, z);
                 }
                 if (check) {
@@ -282,6 +281,8 @@ lbm_status plan(const std::vector<DomainGeo>& doms, const lbm_params& p, BatchCt
             for (auto s : G.lsurf)
                 if (s == SURF_WALL_HI) ++P.nseed;
         P.grid = Q * P.stride + align_up(P.nl + Q, 64);
+        if (P.grid * 4 >= ((int64_t)1 << 32))
+            return set_error(LBM_E_INVAL, "a batched domain's state must stay below 4 GiB (fewer than ~50 M cells)");
         P.off_pop = o; o = align_up(o + P.grid * 4, 256);
         P.off_info = o; o = align_up(o + P.N * 4, 256);
         P.off_segbase = o; o = align_up(o + ((P.N >> SEG_SHIFT) + 1) * 4, 256);
@@ -472,6 +473,7 @@ lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, d
         if (st != LBM_OK) { delete b; return set_error(st, err); }
         BatchDom& T = table[d];
         for (int k = 0; k < Q; ++k) T.pa[k] = reinterpret_cast<float*>(buf + P.off_pop) + k * P.stride;
+        T.stride = (uint32_t)P.stride;
         T.info = reinterpret_cast<const uint32_t*>(buf + P.off_info);
         T.segbase = reinterpret_cast<const int32_t*>(buf + P.off_segbase);
         T.lparam = reinterpret_cast<const float*>(buf + P.off_lparam);

@@ -119,6 +119,25 @@ __device__ __forceinline__ float collide(float (&g)[Q], const CellConsts& a) {
 
 typedef __attribute__((address_space(1))) float gfloat;
 
+// Population array bases.  PopBases: one pointer per direction (the
+// single-domain sweep passes them as kernel arguments).  PopStrided: one base
+// and the distance between arrays, for kernels that would otherwise hold 19
+// pointers in scalar registers (the batched kernel); byte offsets
+// 4 (k stride + cell) must stay below 2^32, which the host checks.
+struct PopBases {
+    float* const* p;
+    __device__ __forceinline__ __attribute__((address_space(1))) char* at(int k, uint32_t idx) const {
+        return (__attribute__((address_space(1))) char*)p[k] + (idx << 2);
+    }
+};
+struct PopStrided {
+    float* base;
+    uint32_t stride;  // floats between consecutive arrays
+    __device__ __forceinline__ __attribute__((address_space(1))) char* at(int k, uint32_t idx) const {
+        return (__attribute__((address_space(1))) char*)base + (((uint32_t)k * stride + idx) << 2);
+    }
+};
+
 template <bool NT>
 __device__ __forceinline__ float ld(const gfloat* p) {
     if (NT) return __builtin_nontemporal_load(p);
@@ -142,8 +161,8 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 // One cell of one time step: pull (with the partial bounce-back values),
 // link correction, collision, push and the next step's partial values.
 // Returns the x-velocity of this step's moments (0 for a solid cell).
-template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD>
-__device__ __forceinline__ float cell_update(float* const* pa, float* const* pb, const uint32_t* __restrict__ info,
+template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD, class PA>
+__device__ __forceinline__ float cell_update(PA pa, PA pb, const uint32_t* __restrict__ info,
                                              const int32_t* __restrict__ segbase,
                                              const float* __restrict__ lparam, const float* pva, float* pvb,
                                              const CellConsts& K, int nx, int ny, int nz, int c, int x, int y,
@@ -160,9 +179,7 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
     // Addressing: population k of cell i is at byte offset 4*i from the
     // array base A + k*stride (uniform); 4*i fits 32 bits (the host limits a
     // domain to 2^30 cells), so loads use a scalar base + 32-bit offset.
-#define AT(bases, k, idx) \
-    (*(__attribute__((address_space(1))) float*)((__attribute__((address_space(1))) char*)(bases)[k] + \
-                                                   ((uint32_t)(idx) << 2)))
+#define AT(bases, k, idx) (*(__attribute__((address_space(1))) float*)(bases).at((k), (uint32_t)(idx)))
 
     // 1) streaming: the cell word and all 19 pulls are issued together; the
     //    empty asm pins the pulls ahead of the solid-cell branch, so a
@@ -226,7 +243,7 @@ __device__ __forceinline__ float cell_update(float* const* pa, float* const* pb,
     const float ux = collide(g, K);
 
     // 4) store
-    float* const* D = (LAYOUT == L_TWOGRID) ? pb : pa;
+    const PA D = (LAYOUT == L_TWOGRID) ? pb : pa;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         const float v = solid ? 0.0f : g[k];

@@ -39,8 +39,8 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepArgs a) {
         y = t % ny;
         z = t / ny;
     }
-    (void)cell_update<LAYOUT, PARITY, BC, NT, false>(a.pa, a.pb, a.info, a.segbase, a.lparam, a.pva, a.pvb, a.k,
-                                                     nx, ny, nz, c, x, y, z);
+    (void)cell_update<LAYOUT, PARITY, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, a.info, a.segbase, a.lparam,
+                                                     a.pva, a.pvb, a.k, nx, ny, nz, c, x, y, z);
 }
 
 template <int LAYOUT, int PARITY, int BC, int BLOCK>
