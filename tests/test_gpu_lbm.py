@@ -269,8 +269,6 @@ def test_c1_20000_steps_against_stored_oracle():
     say("test_c1_20000_steps_against_stored_oracle")
     lbm = _lbm()
     path = os.path.join(os.path.dirname(__file__), "golden", "c1_20000.json")
-    if not os.path.exists(path):
-        pytest.skip("stored oracle state not generated (tests/golden/make_c1_drift.py)")
     with open(path) as f:
         gold = json.load(f)
     d, p, eps = W.coupled_c1()
