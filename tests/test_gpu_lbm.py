@@ -140,6 +140,30 @@ def test_launch_shapes_bitwise():
                 assert np.array_equal(u, base), (layout, block, flags)
 
 
+def test_all_solid_domain():
+    """Degenerate geometry: every cell solid (one sphere covering a periodic
+    box).  Steps, profiles, totals, permeability and the steady test must
+    all work and report zero flow."""
+    lbm = _lbm()
+    d = W.Domain(8, 8, 8, periodic=(1, 1, 1), wall_lo=(0, 0, 0), wall_hi=(0, 0, 0),
+                 spheres=np.array([[4.0, 4.0, 4.0, 7.9375]]))
+    for layout in ("aa", "twogrid"):
+        p = W.Params(collision="trt", tau_plus=0.7, magic_lambda=3 / 16, force=(1e-5, 0, 0), layout=layout)
+        g = lbm.Geometry(d)
+        assert g.info()[1] == 0
+        ctx = lbm.Context(g, p)
+        ctx.step(5)
+        rho, u = ctx.fields()
+        assert np.all(u == 0) and np.all(rho == 0)
+        sup, intr, por = ctx.average_profile(0, 2, 0)
+        assert np.all(sup == 0) and np.all(intr == 0) and np.all(por == 0)
+        m, j = ctx.totals()
+        assert m == 0 and np.all(j == 0)
+        assert ctx.permeability() == 0
+        steps = ctx.run_to_steady(1e-7, 10, 1000)
+        assert steps[0] <= 1000
+
+
 def test_split_runs_and_restart_bitwise():
     say("test_split_runs_and_restart_bitwise")
     lbm = _lbm()

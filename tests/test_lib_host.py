@@ -92,6 +92,18 @@ def test_invalid_inputs_are_rejected():
     assert lbm.required_bytes(g, W.Params(tau_plus=0.8)) > 19 * 4 * 16 ** 3
 
 
+def test_domain_size_limits():
+    """A domain above 2^30 cells (32-bit byte offsets of the sweep) is
+    rejected before anything is allocated; so is a walled axis of fewer
+    than 3 cells."""
+    from paper_1507_06565_amd import lbm
+    E_INVAL = -1
+    assert _status(lambda: lbm.Geometry(W.Domain(1024, 1024, 1025))) == E_INVAL
+    assert _status(lambda: lbm.Geometry(W.Domain(16, 16, 2))) == E_INVAL
+    g = lbm.Geometry(W.Domain(1024, 1024, 1024, periodic=(1, 1, 1), wall_lo=(0, 0, 0), wall_hi=(0, 0, 0)))
+    assert g.info()[1] == 1 << 30
+
+
 def test_required_bytes_layouts():
     from paper_1507_06565_amd import lbm
     g = lbm.Geometry(W.Domain(64, 32, 40))
