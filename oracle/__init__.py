@@ -62,7 +62,7 @@ def lib():
         L.orc_run.argtypes = [P(_ODomain), P(_OParams), C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_void_p]
-        L.orc_gray_run.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+        L.orc_gray_run.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_int64, C.c_void_p]
         L.orc_lattice.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -262,9 +262,11 @@ def totals(rho, u, fluid, rho0=1.0):
 # ----------------------------------------------------------------------------
 
 def gray_run(nz, eps, nu_eff, drag, G=(0.0, 0.0, 0.0), walls=True, lid=(0.0, 0.0, 0.0),
-             magic_lambda=3.0 / 16.0, rho0=1.0, nsteps=1000, g=None):
-    """Advance the gray column; returns (u[nz, 3], g[19, nz])."""
+             magic_lambda=3.0 / 16.0, rho0=1.0, nsteps=1000, g=None, forch=None):
+    """Advance the gray column; returns (u[nz, 3], g[19, nz]).  forch: per-cell
+    Forchheimer coefficient eps F_eps / sqrt(K) of eq. (PorousForce) (None: 0)."""
     eps = np.ascontiguousarray(eps, np.float64)
+    fo = None if forch is None else np.ascontiguousarray(np.broadcast_to(forch, (nz,)), np.float64)
     nu_eff = np.ascontiguousarray(nu_eff, np.float64)
     drag = np.ascontiguousarray(drag, np.float64)
     if g is None:
@@ -273,7 +275,8 @@ def gray_run(nz, eps, nu_eff, drag, G=(0.0, 0.0, 0.0), walls=True, lid=(0.0, 0.0
     u = np.zeros((nz, 3))
     Ga = np.array(G, np.float64)
     La = np.array(lid, np.float64)
-    rc = lib().orc_gray_run(nz, int(walls), _ptr(eps), _ptr(nu_eff), _ptr(drag), magic_lambda, rho0,
+    rc = lib().orc_gray_run(nz, int(walls), _ptr(eps), _ptr(nu_eff), _ptr(drag),
+                            None if fo is None else _ptr(fo), magic_lambda, rho0,
                             _ptr(Ga), _ptr(La), _ptr(g), int(nsteps), _ptr(u))
     if rc == -5:
         raise FloatingPointError("gray column unstable")

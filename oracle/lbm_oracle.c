@@ -510,7 +510,7 @@ int orc_run(const odomain* d, const oparams* p, const int32_t org[3], const int3
  * u_out[3*nz] returns the velocity of the last step.
  * -------------------------------------------------------------------------- */
 int orc_gray_run(int nz, int walls, const double* eps, const double* nu_eff, const double* drag,
-                 double lambda, double rho0, const double G[3], const double uw[3],
+                 const double* forch, double lambda, double rho0, const double G[3], const double uw[3],
                  double* g, int64_t nsteps, double* u_out) {
     tables();
     if (nz < 3) return ORC_INVAL;
@@ -548,13 +548,20 @@ int orc_gray_run(int nz, int walls, const double* eps, const double* nu_eff, con
                 drho += gg[k];
                 j[0] += EX[k] * gg[k]; j[1] += EY[k] * gg[k]; j[2] += EZ[k] * gg[k];
             }
-            const double e = eps[z], D = drag[z];
+            const double e = eps[z], D = drag[z], phi = forch ? forch[z] : 0.0;
             double uu = 0, v[3], uv[3], Ft[3];
-            for (int a = 0; a < 3; ++a) {
-                v[a] = j[a] / rho0 + 0.5 * e * G[a];
-                uv[a] = v[a] / (1.0 + 0.5 * D);
+            for (int a = 0; a < 3; ++a) v[a] = j[a] / rho0 + 0.5 * e * G[a];
+            /* the velocity is implicit in the porous force F = -D u - phi |u| u + eps G
+               (eq. PorousForce): u = v - F(u)/2 solved for u */
+            double den = 1.0 + 0.5 * D;
+            if (phi != 0.0) {
+                const double c0 = 0.5 * (1.0 + 0.5 * D), c1 = 0.5 * phi;
+                const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                den = c0 + sqrt(c0 * c0 + c1 * vn);
             }
-            for (int a = 0; a < 3; ++a) { Ft[a] = -D * uv[a] + e * G[a]; uu += uv[a] * uv[a]; }
+            for (int a = 0; a < 3; ++a) uv[a] = v[a] / den;
+            const double un = sqrt(uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2]);
+            for (int a = 0; a < 3; ++a) { Ft[a] = -D * uv[a] - phi * un * uv[a] + e * G[a]; uu += uv[a] * uv[a]; }
             if (step == nsteps - 1) { u_out[3 * z] = uv[0]; u_out[3 * z + 1] = uv[1]; u_out[3 * z + 2] = uv[2]; }
             if (!(fabs(uv[0]) < 0.4) && !isnan(uv[0])) unstable = 1;
             double geq[19], S[19];

@@ -95,3 +95,26 @@ def test_couette_two_layer_second_order(J):
     # at H = 64, hence the looser bound; the order is what is pinned
     assert errs[1] < 3e-3
     assert errs[0] / errs[1] > 3.5
+
+
+@pytest.mark.parametrize("eps,K,phi,G", [(0.5, 3.0, 0.8, 1e-4), (0.4, 0.5, 2.0, 1e-3), (0.8, 20.0, 0.05, 1e-5)])
+def test_forchheimer_uniform_flow_exact(eps, K, phi, G):
+    """Forchheimer term of eq. (PorousForce): in a uniform periodic column the
+    steady state balances D u + phi u^2 = eps G (D = eps nu / K), so
+    u = (sqrt(D^2 + 4 phi eps G) - D) / (2 phi); it falls below Darcy's K G / nu."""
+    nz = 12
+    D = eps * NU / K
+    u = steady(nz, np.full(nz, eps), np.full(nz, NU), np.full(nz, D), G=(G, 0, 0), walls=False,
+               forch=np.full(nz, phi))
+    exact = (math.sqrt(D * D + 4 * phi * eps * G) - D) / (2 * phi)
+    assert np.max(np.abs(u - exact)) <= 1e-10 * exact
+    assert exact < K * G / NU
+
+
+def test_forchheimer_zero_is_the_stokes_model_bitwise():
+    nz, G = 40, 1e-6
+    eps = np.linspace(0.4, 1.0, nz)
+    drag = np.where(eps < 1, eps * NU / 2.0, 0.0)
+    u0, g0 = oracle.gray_run(nz, eps, NU / eps, drag, G=(G, 0, 0), nsteps=300)
+    u1, g1 = oracle.gray_run(nz, eps, NU / eps, drag, G=(G, 0, 0), nsteps=300, forch=np.zeros(nz))
+    assert np.array_equal(u0, u1) and np.array_equal(g0, g1)
