@@ -6,8 +6,8 @@
  * the porous body force of eq. (PorousForce), discretised as in the cited
  * Guo & Zhao (2002) lattice Boltzmann model, incompressible variant with
  * populations stored as FP32 shifts g = f - w rho0, TRT collision with the
- * magic parameter Lambda, and the Forchheimer coefficient set to zero (the
- * Stokes regime of Sec. 4).
+ * magic parameter Lambda; the Forchheimer term is off by default (the Stokes
+ * regime of Sec. 4) and can be set per cell (gray_set_forchheimer).
  *
  * Geometry: ncols independent columns of 1 x 1 x nz cells (3 <= nz <= 704),
  * periodic along x and y.  With walls != 0 the layers z = 0 and z = nz-1 are
@@ -49,9 +49,17 @@ lbm_status gray_init(int32_t ncols, int32_t nz, int32_t walls, const double* eps
                      const double* drag, double magic_lambda, double rho0, const double* G, const double* lid,
                      void* dev_buf, int64_t bytes, void* hip_stream, gray_ctx** out);
 
-/* Replace the per-cell parameters (e.g. from a closure model) keeping the
- * state; reset the state to rest. */
+/* Replace the per-cell parameters (e.g. from a closure model); the state is
+ * kept (gray_reset restarts from rest). */
 lbm_status gray_set_cells(gray_ctx* ctx, const double* eps, const double* nu_eff, const double* drag);
+
+/* Forchheimer term of eq. (PorousForce): per-cell coefficient
+ * phi = eps F_eps / sqrt(K) >= 0 (ncols*nz doubles, column-major like eps),
+ * adding -phi |u| u to the porous force; the implicit velocity becomes
+ * u = v / (c0 + sqrt(c0^2 + c1 |v|)) with c0 = (1 + drag/2)/2, c1 = phi/2.
+ * NULL clears it (the Stokes model, which is also the default).  The state
+ * is kept.  Errors: LBM_E_INVAL (negative or non-finite coefficient). */
+lbm_status gray_set_forchheimer(gray_ctx* ctx, const double* phi);
 lbm_status gray_reset(gray_ctx* ctx);
 
 /* Advance every column exactly nsteps steps (one launch, LDS-resident). */

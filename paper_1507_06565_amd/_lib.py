@@ -82,6 +82,7 @@ _sig = {
     "mlp_adam_step": ([vp, vp, vp, vp, vp, f64, f64, f64, f64, i64, vp], i32),
     "mlp_windows": ([vp, i32, i32, vp, vp], i32),
     "mlp_closure": ([vp, vp, i64, f64, vp, vp, vp], i32),
+    "gray_set_forchheimer": ([vp, vp], i32),
     "mlp_profile_loss": ([vp, vp, vp, i32, i32, f64, f64, f64, vp, vp, vp], i32),
 }
 

@@ -3,15 +3,17 @@
 // (GeneralizedPor1), (GeneralizedPor2), (PorousForce), discretised as in the
 // cited Guo & Zhao (2002) model, in its incompressible variant with shifted
 // populations and a TRT collision, Forchheimer coefficient zero (Stokes
-// regime, Sec. 4).
+// regime of Sec. 4, unless a Forchheimer coefficient is set).
 //
 // A column is 1 x 1 x nz cells, periodic in x and y, so every population
 // streams along z only.  Per cell: porosity eps, effective viscosity nu_eff
-// (tau+ = 3 nu_eff + 1/2; omega- from the magic parameter) and the Darcy drag
-// coefficient D = eps nu / K (0 in free fluid):
+// (tau+ = 3 nu_eff + 1/2; omega- from the magic parameter), the Darcy drag
+// coefficient D = eps nu / K (0 in free fluid) and, optionally, the
+// Forchheimer coefficient phi = eps F_eps / sqrt(K):
 //   v      = sum_k e_k g_k / rho0 + eps G / 2
-//   u      = v / (1 + D / 2)                     (implicit drag, c_F = 0)
-//   F      = -D u + eps G                        (eq. (PorousForce))
+//   u      = v / (c0 + sqrt(c0^2 + c1 |v|)),  c0 = (1 + D/2)/2, c1 = phi/2
+//            (u = v - F(u)/2 solved for u; u = v / (1 + D/2) when phi = 0)
+//   F      = -D u - phi |u| u + eps G            (eq. (PorousForce))
 //   g_eq_k = w_k [drho + rho0 (3 e.u + 4.5 (e.u)^2 / eps - 1.5 u.u / eps)]
 //   S_k    = w_k rho0 [3 e.F + 9 (e.u)(e.F) / eps - 3 u.F / eps]
 // with S split into even and odd parts relaxed by (1 - omega+/2) and
@@ -39,6 +41,7 @@ namespace lbm {
 struct GrayArgs {
     float* state;         // ncols x 19 x nz
     const float* cell;    // ncols x nz x 4: eps, omega+, omega-, D
+    const float* phi;     // ncols x nz Forchheimer coefficients, or null (all zero)
     double* u;            // ncols x nz x 3
     int64_t* steps;       // per column
     double* uprev;        // per column
@@ -66,10 +69,11 @@ __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
     const bool live = z < nz;
     const bool solid = a.walls && (z == 0 || z == nz - 1);
     float* gs = a.state + (int64_t)col * Q * nz;
-    float eps = 1.0f, wp = 1.0f, wm = 1.0f, D = 0.0f;
+    float eps = 1.0f, wp = 1.0f, wm = 1.0f, D = 0.0f, phi = 0.0f;
     if (live) {
         const float* cp = a.cell + ((int64_t)col * nz + z) * 4;
         eps = cp[0]; wp = cp[1]; wm = cp[2]; D = cp[3];
+        if (a.phi) phi = a.phi[(int64_t)col * nz + z];
 #pragma unroll
         for (int k = 0; k < Q; ++k) lds[k * nz + z] = gs[k * nz + z];
     }
@@ -109,11 +113,23 @@ __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
                 if (L::ez[k]) jz += L::ez[k] * df;
             }
             const float r = 1.0f / a.rho0;
-            const float den = 1.0f / (1.0f + 0.5f * D);
-            ux = (jx * r + 0.5f * Ge[0]) * den;
-            uy = (jy * r + 0.5f * Ge[1]) * den;
-            uz = (jz * r + 0.5f * Ge[2]) * den;
-            const float Fx = -D * ux + Ge[0], Fy = -D * uy + Ge[1], Fz = -D * uz + Ge[2];
+            const float vx = jx * r + 0.5f * Ge[0], vy = jy * r + 0.5f * Ge[1], vz = jz * r + 0.5f * Ge[2];
+            float den = 1.0f / (1.0f + 0.5f * D);
+            if (phi != 0.0f) {
+                const float c0 = 0.5f * (1.0f + 0.5f * D), c1 = 0.5f * phi;
+                const float vn = sqrtf(vx * vx + vy * vy + vz * vz);
+                den = 1.0f / (c0 + sqrtf(c0 * c0 + c1 * vn));
+            }
+            ux = vx * den;
+            uy = vy * den;
+            uz = vz * den;
+            float Fx = -D * ux + Ge[0], Fy = -D * uy + Ge[1], Fz = -D * uz + Ge[2];
+            if (phi != 0.0f) {
+                const float pu = phi * sqrtf(ux * ux + uy * uy + uz * uz);
+                Fx = Fx - pu * ux;
+                Fy = Fy - pu * uy;
+                Fz = Fz - pu * uz;
+            }
             const float uu = ux * ux + uy * uy + uz * uz;
             const float uF = ux * Fx + uy * Fy + uz * Fz;
             {
@@ -185,7 +201,7 @@ struct gray_ctx {
     int ncols = 0, nz = 0, walls = 0;
     hipStream_t stream = nullptr;
     char* buf = nullptr;
-    int64_t off_state = 0, off_cell = 0, off_u = 0, off_steps = 0, off_uprev = 0, off_status = 0;
+    int64_t off_state = 0, off_cell = 0, off_phi = 0, off_u = 0, off_steps = 0, off_uprev = 0, off_status = 0;
     GrayArgs args{};
     double lambda = 3.0 / 16.0, rho0 = 1.0;
     std::vector<int64_t> steps;
@@ -194,7 +210,7 @@ struct gray_ctx {
 namespace {
 
 struct GPlan {
-    int64_t state, cell, u, steps, uprev, status, total;
+    int64_t state, cell, phi, u, steps, uprev, status, total;
 };
 
 GPlan gplan(int ncols, int nz) {
@@ -202,6 +218,7 @@ GPlan gplan(int ncols, int nz) {
     int64_t o = 0;
     P.state = o; o = align_up(o + (int64_t)ncols * Q * nz * 4, 256);
     P.cell = o; o = align_up(o + (int64_t)ncols * nz * 16, 256);
+    P.phi = o; o = align_up(o + (int64_t)ncols * nz * 4, 256);
     P.u = o; o = align_up(o + (int64_t)ncols * nz * 24, 256);
     P.steps = o; o = align_up(o + (int64_t)ncols * 8, 256);
     P.uprev = o; o = align_up(o + (int64_t)ncols * 8, 256);
@@ -287,7 +304,9 @@ lbm_status gray_init(int32_t ncols, int32_t nz, int32_t walls, const double* eps
     const GPlan P = gplan(ncols, nz);
     c->off_state = P.state; c->off_cell = P.cell; c->off_u = P.u; c->off_steps = P.steps; c->off_uprev = P.uprev;
     c->off_status = P.status;
+    c->off_phi = P.phi;
     GrayArgs& a = c->args;
+    a.phi = nullptr;
     a.state = reinterpret_cast<float*>(c->buf + P.state);
     a.cell = reinterpret_cast<const float*>(c->buf + P.cell);
     a.u = reinterpret_cast<double*>(c->buf + P.u);
@@ -324,6 +343,25 @@ lbm_status gray_reset(gray_ctx* c) {
 lbm_status gray_set_cells(gray_ctx* c, const double* eps, const double* nu_eff, const double* drag) {
     if (!c || !eps || !nu_eff || !drag) return set_error(LBM_E_INVAL, "bad arguments");
     return upload_cells(c, eps, nu_eff, drag);
+}
+
+lbm_status gray_set_forchheimer(gray_ctx* c, const double* phi) {
+    if (!c) return set_error(LBM_E_INVAL, "null context");
+    if (!phi) {
+        c->args.phi = nullptr;
+        return LBM_OK;
+    }
+    const int64_t n = (int64_t)c->ncols * c->nz;
+    std::vector<float> f((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(phi[i] >= 0.0) || !std::isfinite(phi[i])) return set_error(LBM_E_INVAL, "Forchheimer coefficients must be >= 0");
+        f[i] = (float)phi[i];
+    }
+    GCHK(hipMemcpyAsync(c->buf + c->off_phi, f.data(), f.size() * 4, hipMemcpyHostToDevice, c->stream),
+         "upload Forchheimer coefficients");
+    GCHK(hipStreamSynchronize(c->stream), "synchronise");
+    c->args.phi = reinterpret_cast<const float*>(c->buf + c->off_phi);
+    return LBM_OK;
 }
 
 lbm_status gray_run(gray_ctx* c, int64_t nsteps) {

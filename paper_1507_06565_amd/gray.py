@@ -52,6 +52,14 @@ class GrayColumns:
         check(lib.gray_set_cells(self.ptr, self._eps.ctypes.data, self._nue.ctypes.data, self._drag.ctypes.data),
               "gray_set_cells")
 
+    def set_forchheimer(self, phi):
+        """Per-cell Forchheimer coefficients eps F_eps / sqrt(K) (None: off)."""
+        if phi is None:
+            check(lib.gray_set_forchheimer(self.ptr, None), "gray_set_forchheimer")
+            return
+        self._phi = _arr(phi, self.ncols, self.nz)
+        check(lib.gray_set_forchheimer(self.ptr, self._phi.ctypes.data), "gray_set_forchheimer")
+
     def reset(self):
         check(lib.gray_reset(self.ptr), "gray_reset")
 
