@@ -307,3 +307,34 @@ def test_c1_20000_steps_against_stored_oracle():
     ep = float(np.linalg.norm(sup - np.array(gold["u_sup"])) / np.linalg.norm(gold["u_sup"]))
     say("C1 20000 steps: sampled cells rel L2", e, "profile rel L2", ep)
     assert e <= REL_L2 and ep <= REL_L2
+
+
+def test_maximum_domain_size_channel():
+    """The largest domain the sweep addresses (2^30 cells, 32-bit byte offsets
+    up to 2^32 - 4): a 1024^3 channel with wall layers in z.  Every plane of
+    the x,y-invariant flow must follow the oracle's narrow column of the same
+    height; mass is conserved exactly (simple bounce-back)."""
+    say("test_maximum_domain_size_channel")
+    import torch
+    lbm = _lbm()
+    free = torch.cuda.mem_get_info()[0]
+    d = W.Domain(1024, 1024, 1024, bc="sbb")
+    p = W.Params(collision="trt", tau_plus=0.8, magic_lambda=3 / 16, force=(1e-5, 0, 0), layout="aa")
+    g = lbm.Geometry(d)
+    need = lbm.required_bytes(g, p)
+    say("required bytes", need, "free", free)
+    assert need < free
+    ctx = lbm.Context(g, p)
+    ctx.step(200)
+    sup, _, por = ctx.average_profile(0, 2, 0)
+    m, j = ctx.totals()
+    del ctx
+    torch.cuda.empty_cache()
+    ref = oracle.Sim(W.Domain(4, 4, 1024, bc="sbb"), p)
+    ref.step(200)
+    rs, _, rp = oracle.plane_profile(ref.velocity(), ref.fluid(), 2, 0)
+    e = float(np.linalg.norm(sup - rs) / np.linalg.norm(rs))
+    say("2^30 cells, 200 steps: profile rel L2", e, "mass", m)
+    assert np.array_equal(por, rp)
+    assert e <= REL_L2
+    assert abs(m) <= 1e-6 * (1 << 30)
