@@ -310,6 +310,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--layout", choices=("aa", "twogrid", "brick"), default="aa",
+                    help="bed: population layout of the sweep")
+    ap.add_argument("--launch", default=None, metavar="BLOCK,FLAGS",
+                    help="bed: fixed launch shape instead of the autotuner (e.g. 1024,2)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--workload", choices=("bed", "rev-batch", "closure-kernels"), default="bed",
@@ -338,6 +342,7 @@ def main():
 
     t0 = time.perf_counter()
     dom, params, eps = W.large_c2()
+    params = W.Params(**{**params.__dict__, "layout": args.layout})
     log(f"workload: {dom.nx}x{dom.ny}x{dom.nz}, {len(dom.spheres)} spheres, bed porosity {eps:.4f} "
         f"({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
@@ -373,7 +378,10 @@ def main():
         torch.cuda.empty_cache()
 
     ctx = lbm.Context(geo, params)
-    if not args.no_autotune:
+    if args.launch:
+        blk, fl = (int(v) for v in args.launch.split(","))
+        ctx.set_launch(blk, fl)
+    elif not args.no_autotune:
         log("autotuned launch (block, flags):", ctx.autotune(10))
     block, flags = ctx.get_launch()
     stream = ctx.stream
@@ -395,7 +403,7 @@ def main():
     mlups = n_cells / (ms_per_step * 1e-3) / 1e6
     mflups = n_fluid / (ms_per_step * 1e-3) / 1e6
     traffic = None
-    tf = os.path.join(ROOT, "profiles", "sweep_aa_512x256x1024_traffic.json")
+    tf = os.path.join(ROOT, "profiles", f"sweep_{args.layout}_512x256x1024_traffic.json")
     if os.path.exists(tf):
         with open(tf) as f:
             tr = json.load(f)
@@ -421,9 +429,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "coupled channel over sphere bed 512x256x1024, radii U[8,16], "
-                               "bed porosity 0.45, TRT Lambda 3/16 tau 0.7, force 5e-7, CLI, AA, FP32 shifted",
+                               f"bed porosity 0.45, TRT Lambda 3/16 tau 0.7, force 5e-7, CLI, {args.layout}, "
+                               "FP32 shifted",
                    "nx": dom.nx, "ny": dom.ny, "nz": dom.nz, "cells": n_cells, "fluid_cells": n_fluid,
-                   "links": n_links, "layout": "aa", "block": block, "launch_flags": flags},
+                   "links": n_links, "layout": args.layout, "block": block, "launch_flags": flags},
         "mflups": round(mflups, 1),
         "effective_gbs": round(achieved, 1),
         "fp32_rel_l2_vs_fp64_oracle": check,

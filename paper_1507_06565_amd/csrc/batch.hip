@@ -153,12 +153,13 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
                 float ux = 0.0f;
                 if (c < N) {
                     const int x = c % nx, t = c / nx, y = t % ny, z = t / ny;
+                    const DenseNb nbi(nx, ny, nz, x, y, z);
                     if (even)
                         ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, pa, info, segbase, lparam, pv, pv,
-                                                                  a.k, nx, ny, nz, c, x, y, z);
+                                                                  a.k, nbi, c);
                     else
                         ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, pa, info, segbase, lparam, pv, pv,
-                                                                 a.k, nx, ny, nz, c, x, y, z);
+                                                                 a.k, nbi, c);
                 }
                 if (check) {
                     const double w = wave_sum((double)ux);
@@ -469,7 +470,7 @@ lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, d
         const DomPlan& P = b->plans[d];
         DeviceImages im;
         std::string err;
-        st = build_images(doms[d], LBM_LAYOUT_AA, P.stride, b->k, im, err);
+        st = build_images(doms[d], LBM_LAYOUT_AA, BrickMap{}, P.stride, b->k, im, err);
         if (st != LBM_OK) { delete b; return set_error(st, err); }
         BatchDom& T = table[d];
         for (int k = 0; k < Q; ++k) T.pa[k] = reinterpret_cast<float*>(buf + P.off_pop) + k * P.stride;

@@ -1,7 +1,7 @@
 // C ABI of the pore-scale solver: geometry objects, contexts bound to a
 // caller-owned device buffer and stream, stepping, FP64 reductions,
 // checkpointing and the sweep autotuner.  Single-domain contexts run the
-// fused sweep (two-grid or AA); multi-domain contexts run the batched
+// fused sweep (two-grid, AA or brick); multi-domain contexts run the batched
 // persistent kernel (batch.hip).
 #include <hip/hip_runtime.h>
 
@@ -60,25 +60,36 @@ lbm_status rates(const lbm_params& p, double& wp, double& wm) {
     wp = 1.0 / p.tau_plus;
     wm = 1.0 / tm;
     if (!(wm > 0.0 && wm < 2.0)) return fail(LBM_E_INVAL, "omega- must lie in (0, 2)");
-    if (p.layout != LBM_LAYOUT_TWOGRID && p.layout != LBM_LAYOUT_AA) return fail(LBM_E_INVAL, "unknown layout");
+    if (p.layout != LBM_LAYOUT_TWOGRID && p.layout != LBM_LAYOUT_AA && p.layout != LBM_LAYOUT_BRICK)
+        return fail(LBM_E_INVAL, "unknown layout");
     return LBM_OK;
 }
 
 // --------------------------------------------------------- memory plan --
 struct Plan {
     int64_t N = 0, stride = 0, nb = 0, nl = 0, np = 0, chunk = 0, nseed = 0;
+    int64_t NS = 0;            // stored cells (N, or 64 per stored brick)
+    int64_t nbricks = 0, nbmap = 0;  // brick layout: stored bricks, entries of the brick map
     int64_t grid = 0;  // floats per state block: Q population arrays + the partial values
     int64_t off_pop = 0, off_info = 0, off_segbase = 0, off_lparam = 0, off_seed = 0, off_red = 0, off_fields = 0;
+    int64_t off_nbr = 0, off_bmap = 0;
     int64_t total = 0;
 };
 
-Plan plan_single(const DomainGeo& g, const lbm_params& p) {
+// bm: the brick map (counts only) for the brick layout, else unused
+Plan plan_single(const DomainGeo& g, const lbm_params& p, const BrickMap& bm) {
     Plan P;
     const auto& d = g.desc;
     P.N = g.ncells();
+    const bool brick = p.layout == LBM_LAYOUT_BRICK;
+    P.NS = brick ? bm.nstored * 64 : P.N;
+    if (brick) {
+        P.nbricks = bm.nstored;
+        P.nbmap = (int64_t)bm.bx * bm.by * bm.bz;
+    }
     // pad each population array so that the 19 arrays do not start on the
     // same power-of-two boundary (HBM channel interleave)
-    P.stride = align_up(P.N, 256) + 320;
+    P.stride = align_up(P.NS, 256) + 320;
     P.nl = (int64_t)g.lcell.size();
     int64_t nb = 0;
     for (size_t i = 0; i < g.lcell.size(); ++i)
@@ -91,11 +102,13 @@ Plan plan_single(const DomainGeo& g, const lbm_params& p) {
     P.np = std::max(d.nx, std::max(d.ny, d.nz));
     P.chunk = std::min<int64_t>(P.N, std::max<int64_t>((int64_t)d.nx * d.ny, 1 << 20));
     int64_t o = 0;
-    const int64_t ngrid = (p.layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
+    const int64_t ngrid = (p.layout == LBM_LAYOUT_AA) ? 1 : 2;
     P.grid = Q * P.stride + align_up(P.nl + Q, 64);
     P.off_pop = o; o = align_up(o + ngrid * P.grid * 4, 256);
-    P.off_info = o; o = align_up(o + P.N * 4, 256);
-    P.off_segbase = o; o = align_up(o + ((P.N >> SEG_SHIFT) + 1) * 4, 256);
+    P.off_info = o; o = align_up(o + P.NS * 4, 256);
+    P.off_segbase = o; o = align_up(o + ((P.NS >> SEG_SHIFT) + 1) * 4, 256);
+    P.off_nbr = o; o = align_up(o + P.nbricks * 27 * 4, 256);
+    P.off_bmap = o; o = align_up(o + P.nbmap * 4, 256);
     P.off_lparam = o; o = align_up(o + (P.nl + Q) * 4, 256);
     P.off_seed = o; o = align_up(o + std::max<int64_t>(P.nseed, 1) * 12, 256);
     P.off_red = o; o = align_up(o + P.np * 6 * 8, 256);
@@ -148,6 +161,7 @@ MomentArgs moment_args(const lbm_ctx* c) {
     m.A = reinterpret_cast<const float*>(c->buf + c->P.off_pop) + (int64_t)c->cur * c->P.grid;
     m.stride = c->P.stride;
     m.info = reinterpret_cast<const uint32_t*>(c->buf + c->P.off_info);
+    m.bmap = c->p.layout == LBM_LAYOUT_BRICK ? reinterpret_cast<const int32_t*>(c->buf + c->P.off_bmap) : nullptr;
     m.nx = c->d.nx; m.ny = c->d.ny; m.nz = c->d.nz;
     m.layout = c->p.layout;
     m.parity = c->parity;
@@ -223,7 +237,7 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
         SweepArgs a = c->sa;
         float* base = reinterpret_cast<float*>(c->buf + c->P.off_pop);
         int par = P_EVEN;
-        if (c->p.layout == LBM_LAYOUT_TWOGRID) {
+        if (c->p.layout != LBM_LAYOUT_AA) {
             a.A = base + (int64_t)c->cur * c->P.grid;
             a.B = base + (int64_t)(1 - c->cur) * c->P.grid;
         } else {
@@ -241,7 +255,7 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
         a.nt = c->nt;
         hipError_t e = launch_sweep(a, c->p.layout, par, c->d.bc, c->block, c->stream);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
-        if (c->p.layout == LBM_LAYOUT_TWOGRID) c->cur = 1 - c->cur;
+        if (c->p.layout != LBM_LAYOUT_AA) c->cur = 1 - c->cur;
         else c->parity = par;
         ++c->steps;
     }
@@ -251,7 +265,7 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
 // rest state: every population and partial value zero (f = w rho0), the
 // moving-wall partial values seeded
 hipError_t reset_state(lbm_ctx* c) {
-    const int64_t ngrid = (c->p.layout == LBM_LAYOUT_TWOGRID) ? 2 : 1;
+    const int64_t ngrid = (c->p.layout == LBM_LAYOUT_AA) ? 1 : 2;
     float* pop = reinterpret_cast<float*>(c->buf + c->P.off_pop);
     hipError_t e = launch_fill_zero(pop, ngrid * c->P.grid, c->stream);
     if (e == hipSuccess && c->P.nseed > 0)
@@ -330,7 +344,12 @@ lbm_status lbm_required_bytes(const lbm_geometry* g, const lbm_params* p, int64_
     lbm_status s = rates(*p, wp, wm);
     if (s != LBM_OK) return s;
     if (g->doms.size() == 1) {
-        *bytes = plan_single(g->doms[0], *p).total;
+        BrickMap bm;
+        if (p->layout == LBM_LAYOUT_BRICK) {
+            if (!brick_dims_ok(g->doms[0].desc)) return fail(LBM_E_INVAL, "brick layout needs nx, ny, nz divisible by 4");
+            build_brick_map(g->doms[0], bm, false);
+        }
+        *bytes = plan_single(g->doms[0], *p, bm).total;
         return LBM_OK;
     }
     return batch_required_bytes(g->doms, *p, bytes);
@@ -365,10 +384,23 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
         return LBM_OK;
     }
     const DomainGeo& G = g->doms[0];
+    BrickMap bm;
+    if (p->layout == LBM_LAYOUT_BRICK) {
+        if (!brick_dims_ok(G.desc)) {
+            delete c;
+            return fail(LBM_E_INVAL, "brick layout needs nx, ny, nz divisible by 4");
+        }
+        try {
+            build_brick_map(G, bm, true);
+        } catch (const std::bad_alloc&) {
+            delete c;
+            return fail(LBM_E_NOMEM, "host memory for the brick map");
+        }
+    }
     c->d = G.desc;
     c->d.spheres = nullptr;
     c->d.n_spheres = 0;
-    c->P = plan_single(G, *p);
+    c->P = plan_single(G, *p, bm);
     c->n_fluid = G.n_fluid;
     if (bytes < c->P.total) {
         delete c;
@@ -379,8 +411,14 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
     DeviceImages im;
     {
         std::string err;
-        lbm_status st = build_images(G, p->layout, c->P.stride, make_consts(*p, wp, wm, G.desc.wall_hi_velocity), im,
-                                     err);
+        lbm_status st = LBM_OK;
+        try {
+            st = build_images(G, p->layout, bm, c->P.stride, make_consts(*p, wp, wm, G.desc.wall_hi_velocity), im,
+                              err);
+        } catch (const std::bad_alloc&) {
+            st = LBM_E_NOMEM;
+            err = "host memory for the device images";
+        }
         if (st != LBM_OK) {
             delete c;
             return fail(st, err);
@@ -393,6 +431,8 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
     a.segbase = reinterpret_cast<const int32_t*>(c->buf + c->P.off_segbase);
     a.lparam = reinterpret_cast<const float*>(c->buf + c->P.off_lparam);
     a.nx = nx; a.ny = ny; a.nz = nz; a.ncells = (int32_t)N;
+    a.nbr = reinterpret_cast<const int32_t*>(c->buf + c->P.off_nbr);
+    a.nbricks = (int32_t)c->P.nbricks;
     a.k = make_consts(*p, wp, wm, G.desc.wall_hi_velocity);
     // launch configuration from the tuning cache, if any
     {
@@ -420,8 +460,13 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
                                hipMemcpyHostToDevice, c->stream);
     }
     if (e == hipSuccess) e = reset_state(c);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(c->buf + c->P.off_info, info.data(), N * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && (int64_t)info.size() != c->P.NS) e = hipErrorInvalidValue;
+    if (e == hipSuccess && c->P.NS > 0)
+        e = hipMemcpyAsync(c->buf + c->P.off_info, info.data(), c->P.NS * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->P.nbricks > 0)
+        e = hipMemcpyAsync(c->buf + c->P.off_nbr, bm.nbr.data(), bm.nbr.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->P.nbmap > 0)
+        e = hipMemcpyAsync(c->buf + c->P.off_bmap, bm.id.data(), bm.id.size() * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->buf + c->P.off_segbase, segbase.data(), segbase.size() * 4, hipMemcpyHostToDevice,
                            c->stream);

@@ -26,6 +26,12 @@
 // lines cost extra HBM cycles.  No cell reads a solid cell's slots (the pull
 // of a link direction is replaced by P), so the zeros are never used.
 //
+// Brick layout: the cells of every 4x4x4 brick that holds a fluid cell are
+// stored together (local index lx + 4 ly + 16 lz, so a 32-lane group is one
+// 4x4x2 half-brick and one 128-byte line); bricks without fluid are not
+// stored.  It streams like the two-grid layout (pull from x - e_k, aligned
+// store at x), with the source found through the brick's neighbour table.
+//
 // AA state locations: after an even step gt_k(x) is stored at A[kbar][x];
 // after an odd step at A[k][x + e_k].  An even step reads A[k][x] and writes
 // A[kbar][x]; an odd step reads A[kbar][x - e_k] and writes A[k][x + e_k].
@@ -158,23 +164,70 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
     return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
+// Index of the neighbour x + (dx, dy, dz) of a cell in the dense layouts
+// (x fastest, every axis wrapped; walls are solid cells of the grid).  All
+// indices are below 2^31.
+struct DenseNb {
+    unsigned X[3], Y[3], Z[3], nx, ny;
+    __device__ __forceinline__ DenseNb(int nx_, int ny_, int nz_, int x, int y, int z) {
+        X[0] = (unsigned)(x == 0 ? nx_ - 1 : x - 1); X[1] = (unsigned)x; X[2] = (unsigned)(x == nx_ - 1 ? 0 : x + 1);
+        Y[0] = (unsigned)(y == 0 ? ny_ - 1 : y - 1); Y[1] = (unsigned)y; Y[2] = (unsigned)(y == ny_ - 1 ? 0 : y + 1);
+        Z[0] = (unsigned)(z == 0 ? nz_ - 1 : z - 1); Z[1] = (unsigned)z; Z[2] = (unsigned)(z == nz_ - 1 ? 0 : z + 1);
+        nx = (unsigned)nx_;
+        ny = (unsigned)ny_;
+    }
+    __device__ __forceinline__ unsigned operator()(int dx, int dy, int dz) const {
+        return X[dx + 1] + nx * (Y[dy + 1] + ny * Z[dz + 1]);
+    }
+};
+
+// Same in the brick layout: lane l of a wavefront is cell l of its brick,
+// and lane j < 27 holds the stored index of the neighbouring brick in
+// direction (j % 3 - 1, j / 3 % 3 - 1, j / 9 - 1) (wrapped; a brick without
+// fluid is replaced by the brick itself, whose values are then never used:
+// a fluid cell pulls from a cell of such a brick only along a link).  A cell
+// on a face of its brick can only leave it through that face, so each lane
+// needs at most six neighbour bricks (its x, y and z sides and their three
+// pairwise edges); they are fetched once, across lanes, by the constructor,
+// which every lane of the wavefront must run together.
+struct BrickNb {
+    int own;               // this brick
+    int lx, ly, lz;        // local coordinates, 0..3
+    int sx, sy, sz;        // side of the brick the cell touches per axis: -1, 0 or +1
+    int bX, bY, bZ, bXY, bXZ, bYZ;
+    __device__ __forceinline__ BrickNb(int table, int own_, int l) {
+        own = own_;
+        lx = l & 3; ly = (l >> 2) & 3; lz = l >> 4;
+        sx = lx == 0 ? -1 : (lx == 3 ? 1 : 0);
+        sy = ly == 0 ? -1 : (ly == 3 ? 1 : 0);
+        sz = lz == 0 ? -1 : (lz == 3 ? 1 : 0);
+        bX = __shfl(table, 13 + sx, 64);
+        bY = __shfl(table, 13 + 3 * sy, 64);
+        bZ = __shfl(table, 13 + 9 * sz, 64);
+        bXY = __shfl(table, 13 + sx + 3 * sy, 64);
+        bXZ = __shfl(table, 13 + sx + 9 * sz, 64);
+        bYZ = __shfl(table, 13 + 3 * sy + 9 * sz, 64);
+    }
+    __device__ __forceinline__ unsigned operator()(int dx, int dy, int dz) const {
+        const bool cx = dx != 0 && dx == sx, cy = dy != 0 && dy == sy, cz = dz != 0 && dz == sz;
+        const int src = cx ? (cy ? bXY : (cz ? bXZ : bX)) : (cy ? (cz ? bYZ : bY) : (cz ? bZ : own));
+        return (unsigned)src * 64u + (unsigned)(((lx + dx) & 3) + 4 * ((ly + dy) & 3) + 16 * ((lz + dz) & 3));
+    }
+};
+
 // One cell of one time step: pull (with the partial bounce-back values),
 // link correction, collision, push and the next step's partial values.
-// Returns the x-velocity of this step's moments (0 for a solid cell).
-template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD, class PA>
+// Returns the x-velocity of this step's moments (0 for a solid cell).  c is
+// the cell's index in the population arrays, nbi(dx, dy, dz) that of its
+// neighbour (DenseNb or BrickNb).
+template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD, class PA, class NBI>
 __device__ __forceinline__ float cell_update(PA pa, PA pb, const uint32_t* __restrict__ info,
                                              const int32_t* __restrict__ segbase,
                                              const float* __restrict__ lparam, const float* pva, float* pvb,
-                                             const CellConsts& K, int nx, int ny, int nz, int c, int x, int y,
-                                             int z) {
+                                             const CellConsts& K, const NBI& nbi, int c) {
 #pragma clang fp contract(off)
-    const unsigned X[3] = {(unsigned)(x == 0 ? nx - 1 : x - 1), (unsigned)x, (unsigned)(x == nx - 1 ? 0 : x + 1)};
-    const unsigned Y[3] = {(unsigned)(y == 0 ? ny - 1 : y - 1), (unsigned)y, (unsigned)(y == ny - 1 ? 0 : y + 1)};
-    const unsigned Z[3] = {(unsigned)(z == 0 ? nz - 1 : z - 1), (unsigned)z, (unsigned)(z == nz - 1 ? 0 : z + 1)};
-    const unsigned unx = (unsigned)nx, uny = (unsigned)ny;
     const unsigned uc = (unsigned)c;
-    // linear index of x + (dx, dy, dz); all indices are below 2^31
-#define NB(dx, dy, dz) (X[(dx) + 1] + unx * (Y[(dy) + 1] + uny * Z[(dz) + 1]))
+#define NB(dx, dy, dz) nbi((dx), (dy), (dz))
 
     // Addressing: population k of cell i is at byte offset 4*i from the
     // array base A + k*stride (uniform); 4*i fits 32 bits (the host limits a

@@ -31,7 +31,7 @@ lbm_status build_domain(const lbm_domain_desc& d, DomainGeo& out, std::string& e
 lbm_status set_error(lbm_status s, const std::string& msg);
 
 // ----------------------------------------------------------- device layout --
-// One 32-bit word per cell:
+// One 32-bit word per stored cell (c: its index in the population arrays):
 //   CELL_SOLID_WORD (all ones)  solid cell, not updated;
 //   otherwise bits 0..17 are the link mask (bit k-1 set if x + e_k is solid)
 //   and bits 18..31 the offset of the cell's first link from the first link
@@ -42,7 +42,7 @@ constexpr uint32_t CELL_SOLID_WORD = 0xFFFFFFFFu;
 constexpr int SEG_SHIFT = 9;
 constexpr uint32_t LINK_MASK_BITS = 0x3FFFFu;
 
-enum Layout : int { L_TWOGRID = 0, L_AA = 1 };
+enum Layout : int { L_TWOGRID = 0, L_AA = 1, L_BRICK = 2 };
 enum Parity : int { P_EVEN = 0, P_ODD = 1 };
 
 // collision constants shared by every cell of a run
@@ -79,10 +79,27 @@ struct SweepArgs {
     float* pva;           // partial bounce-back values read this step (one per link)
     float* pvb;           // ... and written for the next step (AA: pva == pvb)
     int32_t nx, ny, nz, ncells;
+    const int32_t* nbr;   // brick layout: 27 neighbour bricks per stored brick
+    int32_t nbricks;      // brick layout: stored bricks
     CellConsts k;
     int32_t xcd_remap;
     int32_t nt;           // non-temporal hints on the aligned streams
 };
+
+// Brick layout (4x4x4 bricks, bricks without fluid cells not stored): map
+// from the dense brick index (bx + BX (by + BY bz)) to the stored brick
+// (-1: not stored) and, per stored brick, the stored neighbours in the 27
+// directions j = (dx+1) + 3 (dy+1) + 9 (dz+1), wrapped, with the brick itself
+// in place of a brick that is not stored.
+constexpr int BRICK = 4;
+struct BrickMap {
+    int32_t bx = 0, by = 0, bz = 0;  // bricks per axis
+    int64_t nstored = 0;
+    std::vector<int32_t> id;         // bx*by*bz
+    std::vector<int32_t> nbr;        // 27 * nstored
+};
+bool brick_dims_ok(const lbm_domain_desc& d);
+void build_brick_map(const DomainGeo& G, BrickMap& bm, bool with_table);
 
 struct DeviceImages {
     std::vector<uint32_t> info;
@@ -91,8 +108,10 @@ struct DeviceImages {
     std::vector<int64_t> seed_idx;
     std::vector<float> seed_val;
 };
-lbm_status build_images(const DomainGeo& G, int layout, int64_t stride, const CellConsts& K, DeviceImages& im,
-                        std::string& err);
+// cell words, link records and seeds in the storage order of the layout
+// (bm: the brick map for L_BRICK, else unused)
+lbm_status build_images(const DomainGeo& G, int layout, const BrickMap& bm, int64_t stride, const CellConsts& K,
+                        DeviceImages& im, std::string& err);
 
 CellConsts make_consts(const lbm_params& p, double wp, double wm, const double* wall_velocity);
 
@@ -102,6 +121,7 @@ struct MomentArgs {
     const float* A;
     int64_t stride;
     const uint32_t* info;
+    const int32_t* bmap;     // brick layout: dense brick -> stored brick (-1: none); else null
     int32_t nx, ny, nz;
     int32_t layout, parity;  // parity of the last step taken (AA); -1: no step yet
     double rho0;

@@ -16,9 +16,10 @@ namespace {
 
 using L = D3Q19;
 
-// post-collision population k of cell c in the current state
+// post-collision population k of cell (x, y, z), stored at index c, in the
+// current state
 __device__ __forceinline__ float post(const MomentArgs& a, int k, int c, int x, int y, int z) {
-    if (a.layout == L_TWOGRID || a.parity < 0) return a.A[k * a.stride + c];
+    if (a.layout != L_AA || a.parity < 0) return a.A[k * a.stride + c];
     if (a.parity == P_EVEN) return a.A[opp(k) * a.stride + c];
     int xn = x + L::ex[k], yn = y + L::ey[k], zn = z + L::ez[k];
     xn = xn < 0 ? a.nx - 1 : (xn == a.nx ? 0 : xn);
@@ -29,8 +30,14 @@ __device__ __forceinline__ float post(const MomentArgs& a, int k, int c, int x, 
 
 __device__ __forceinline__ bool cell_moments(const MomentArgs& a, int c, double& rho, double& ux, double& uy,
                                              double& uz) {
-    if (a.info[c] == CELL_SOLID_WORD) return false;
     const int x = c % a.nx, t = c / a.nx, y = t % a.ny, z = t / a.ny;
+    if (a.bmap) {
+        // brick layout: cells of bricks that are not stored are solid
+        const int b = a.bmap[(x >> 2) + (a.nx >> 2) * ((y >> 2) + (a.ny >> 2) * (z >> 2))];
+        if (b < 0) return false;
+        c = b * 64 + (x & 3) + 4 * (y & 3) + 16 * (z & 3);
+    }
+    if (a.info[c] == CELL_SOLID_WORD) return false;
     double s = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {

@@ -1,5 +1,6 @@
-// Single-domain sweep kernel: maps workgroups to cells and runs the fused
-// stream + collide update of cell.hpp on every cell of the domain.
+// Single-domain sweep kernels: map workgroups to cells (dense layouts) or to
+// bricks (brick layout) and run the fused stream + collide update of cell.hpp
+// on every stored cell of the domain.
 #include <hip/hip_runtime.h>
 
 #include "cell.hpp"
@@ -39,23 +40,49 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepArgs a) {
         y = t % ny;
         z = t / ny;
     }
+    const DenseNb nbi(nx, ny, nz, x, y, z);
     (void)cell_update<LAYOUT, PARITY, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, a.info, a.segbase, a.lparam,
-                                                     a.pva, a.pvb, a.k, nx, ny, nz, c, x, y, z);
+                                                     a.pva, a.pvb, a.k, nbi, c);
+}
+
+// Brick layout: one wavefront per stored brick, lane l = cell l of the brick
+// (lx + 4 ly + 16 lz); the pull goes through the brick's neighbour table and
+// the store is aligned, as in the two-grid layout.
+template <int BC, int BLOCK, bool NT>
+__global__ void __launch_bounds__(BLOCK) k_sweep_brick(SweepArgs a) {
+    int b = blockIdx.x;
+    if (a.xcd_remap) b = remap_block(b, gridDim.x);
+    const int brick = b * (BLOCK / 64) + (int)(threadIdx.x >> 6);  // uniform per wavefront
+    if (brick >= a.nbricks) return;
+    const int l = threadIdx.x & 63;
+    const BrickNb nbi(a.nbr[(int64_t)brick * 27 + (l < 27 ? l : 13)], brick, l);
+    (void)cell_update<L_TWOGRID, P_EVEN, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, a.info, a.segbase,
+                                                        a.lparam, a.pva, a.pvb, a.k, nbi, brick * 64 + l);
 }
 
 template <int LAYOUT, int PARITY, int BC, int BLOCK>
 hipError_t launch4(const SweepArgs& a, hipStream_t s) {
-    const unsigned nb = (unsigned)(((int64_t)a.ncells + BLOCK - 1) / BLOCK);
-    const bool row = (a.nx % BLOCK) == 0;
-    if (row && a.nt)
-        k_sweep<LAYOUT, PARITY, BC, BLOCK, true, true><<<nb, BLOCK, 0, s>>>(a);
-    else if (row)
-        k_sweep<LAYOUT, PARITY, BC, BLOCK, true, false><<<nb, BLOCK, 0, s>>>(a);
-    else if (a.nt)
-        k_sweep<LAYOUT, PARITY, BC, BLOCK, false, true><<<nb, BLOCK, 0, s>>>(a);
-    else
-        k_sweep<LAYOUT, PARITY, BC, BLOCK, false, false><<<nb, BLOCK, 0, s>>>(a);
-    return hipGetLastError();
+    if constexpr (LAYOUT == L_BRICK) {
+        const unsigned nb = (unsigned)(((int64_t)a.nbricks + BLOCK / 64 - 1) / (BLOCK / 64));
+        if (nb == 0) return hipSuccess;
+        if (a.nt)
+            k_sweep_brick<BC, BLOCK, true><<<nb, BLOCK, 0, s>>>(a);
+        else
+            k_sweep_brick<BC, BLOCK, false><<<nb, BLOCK, 0, s>>>(a);
+        return hipGetLastError();
+    } else {
+        const unsigned nb = (unsigned)(((int64_t)a.ncells + BLOCK - 1) / BLOCK);
+        const bool row = (a.nx % BLOCK) == 0;
+        if (row && a.nt)
+            k_sweep<LAYOUT, PARITY, BC, BLOCK, true, true><<<nb, BLOCK, 0, s>>>(a);
+        else if (row)
+            k_sweep<LAYOUT, PARITY, BC, BLOCK, true, false><<<nb, BLOCK, 0, s>>>(a);
+        else if (a.nt)
+            k_sweep<LAYOUT, PARITY, BC, BLOCK, false, true><<<nb, BLOCK, 0, s>>>(a);
+        else
+            k_sweep<LAYOUT, PARITY, BC, BLOCK, false, false><<<nb, BLOCK, 0, s>>>(a);
+        return hipGetLastError();
+    }
 }
 
 template <int LAYOUT, int PARITY, int BC>
@@ -101,6 +128,7 @@ hipError_t launch_scatter(float* p, const int64_t* idx, const float* val, int64_
 
 hipError_t launch_sweep(const SweepArgs& a, int layout, int parity, int bc, int block, hipStream_t s) {
     if (layout == L_TWOGRID) return launch2<L_TWOGRID, P_EVEN>(a, bc, block, s);
+    if (layout == L_BRICK) return launch2<L_BRICK, P_EVEN>(a, bc, block, s);
     if (parity == P_EVEN) return launch2<L_AA, P_EVEN>(a, bc, block, s);
     return launch2<L_AA, P_ODD>(a, bc, block, s);
 }

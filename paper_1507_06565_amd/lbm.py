@@ -14,7 +14,7 @@ from ._lib import DomainDesc, LbmError, Params, Sphere, check, lib  # noqa: F401
 
 BC = {"sbb": 0, "cli": 1, "bouzidi": 2}
 COLLISION = {"bgk": 0, "trt": 1}
-LAYOUT = {"twogrid": 0, "aa": 1}
+LAYOUT = {"twogrid": 0, "aa": 1, "brick": 2}
 
 
 def _desc(dom, keep):

@@ -114,6 +114,33 @@ def test_required_bytes_layouts():
     assert two - aa >= 19 * 4 * 64 * 32 * 40 - 4 * nl - 4096
 
 
+def test_brick_layout_plan():
+    """The brick layout stores only 4x4x4 bricks that hold fluid (two grids of
+    them), and rejects sizes not divisible by 4."""
+    import numpy as np
+
+    import oracle
+    from paper_1507_06565_amd import lbm
+    E_INVAL = -1
+    S = np.array([[16.0, 16.0, 16.0, 11.0], [40.0, 20.0, 30.0, 9.0]])
+    d = W.Domain(48, 32, 40, spheres=S)
+    g = lbm.Geometry(d)
+    two = lbm.required_bytes(g, W.Params(layout="twogrid"))
+    brick = lbm.required_bytes(g, W.Params(layout="brick"))
+    f = oracle.flags(d) == 0
+    stored = int(f.reshape(10, 4, 8, 4, 12, 4).any(axis=(1, 3, 5)).sum())
+    assert stored < 12 * 8 * 10
+    dropped = (12 * 8 * 10 - stored) * 64
+    # two grids of 19 arrays lose the dropped cells; 27 neighbours per stored
+    # brick and one map entry per brick are added
+    assert two - brick >= 2 * 19 * 4 * dropped - 27 * 4 * stored - 4 * 12 * 8 * 10 - 8192
+    assert two - brick <= 2 * 19 * 4 * dropped + 8192
+    for shape in ((30, 32, 40), (48, 34, 40), (48, 32, 42)):
+        gb = lbm.Geometry(W.Domain(*shape))
+        assert _status(lambda: lbm.required_bytes(gb, W.Params(layout="brick"))) == E_INVAL
+        assert lbm.required_bytes(gb, W.Params(layout="twogrid")) > 0
+
+
 def test_closure_and_gray_argument_validation():
     """Size and pointer checks of the gray and network entry points, which
     return before any device work."""
