@@ -3,15 +3,17 @@
 Workload (default): the large coupled free-channel / porous-bed domain,
 512 x 256 x 1024 cells, sphere bed (radii U[8,16], porosity 0.45) in the lower
 half, TRT with Lambda = 3/16, tau+ = 0.7, body force 5e-7, CLI bounce-back at
-the spheres, FP32 shifted populations in the AA in-place layout.  One step is
-one full time step of the hot path: the fused stream + collide sweep with
-the interpolated bounce-back of every boundary link.  Inputs are resident in
-HBM before the timed region starts.
+the spheres, FP32 shifted populations in the brick layout (4x4x4 bricks, the
+all-solid ones not stored, pull streaming between two grids; --layout aa or
+twogrid selects the dense layouts).  One step is one full time step of the hot
+path: the fused stream + collide sweep with the interpolated bounce-back of
+every boundary link.  Inputs are resident in HBM before the timed region
+starts.
 
 Prints ONE JSON line (rank 0) with MLUPS as `value`, plus the roofline of the
 sweep kernel and the CPU oracle's rate on a bounded sample of the workload.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-check]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-check] [--layout L]
     python bench.py --workload rev-batch [--samples 512] [--out profiles.json]
 
 The second form times the batched REV workload (512 periodic cubes to steady
@@ -310,7 +312,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
-    ap.add_argument("--layout", choices=("aa", "twogrid", "brick"), default="aa",
+    ap.add_argument("--layout", choices=("aa", "twogrid", "brick"), default="brick",
                     help="bed: population layout of the sweep")
     ap.add_argument("--launch", default=None, metavar="BLOCK,FLAGS",
                     help="bed: fixed launch shape instead of the autotuner (e.g. 1024,2)")

@@ -235,14 +235,17 @@ def test_c1_full_size_parity():
 
 # ------------------------------------------------------------------ C2 ---
 
-def test_c2_full_size_sampled_windows():
-    """C2 at full size (512x256x1024, AA, CLI, TRT 3/16, tau 0.7) in the launch
-    configuration the benchmark uses: 8 steps from rest, then sampled cells
-    against oracle windows whose edge is more than 8 cells away (the light
-    cone of 8 steps); also the bed porosity and plane porosity profile."""
-    say("test_c2_full_size_sampled_windows")
+@pytest.mark.parametrize("layout", ["brick", "aa"])
+def test_c2_full_size_sampled_windows(layout):
+    """C2 at full size (512x256x1024, CLI, TRT 3/16, tau 0.7) in the launch
+    configuration the benchmark uses (brick layout, autotuned; and the AA
+    layout): 8 steps from rest, then sampled cells against oracle windows
+    whose edge is more than 8 cells away (the light cone of 8 steps); also the
+    bed porosity and plane porosity profile."""
+    say("test_c2_full_size_sampled_windows", layout)
     lbm = _lbm()
     d, p, eps = W.large_c2()
+    p = W.Params(**{**p.__dict__, "layout": layout})
     assert abs(eps - 0.45) <= 0.01
     g = lbm.Geometry(d)
     ctx = lbm.Context(g, p)
