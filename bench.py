@@ -120,7 +120,9 @@ def rev_batch(args):
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
         gen = sorted(pool.map(_gen_rev, range(n), chunksize=4), key=lambda r: r[0])
     doms = [g[1] for g in gen]
-    params = gen[0][2]
+    from paper_1507_06565_amd import workloads as W
+    layout = "brick" if args.layout == "brick" else "aa"  # a batch runs AA or bricks
+    params = W.Params(**{**gen[0][2].__dict__, "layout": layout})
     log(f"{n} REV samples generated ({time.perf_counter() - t0:.1f} s); edges "
         f"{dict(zip(*np.unique([d.nx for d in doms], return_counts=True)))}")
 
@@ -136,8 +138,34 @@ def rev_batch(args):
         f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.set_device(0)
     ctx = lbm.Context(geo, params)
-    block, W0 = ctx.autotune(10) if not args.no_autotune else ctx.batch_get_launch()
-    log(f"autotuned batched launch (block, workgroups per sample): ({block}, {W0})")
+    if args.launch:
+        block, W0 = (int(v) for v in args.launch.split(","))
+        ctx.batch_set_launch(block, W0)
+    else:
+        block, W0 = ctx.autotune(10) if not args.no_autotune else ctx.batch_get_launch()
+    log(f"batched launch (block, workgroups per sample): ({block}, {W0})")
+    if args.fixed_steps > 0:
+        # every cube active: the batched kernel's steady throughput and bytes per step
+        if args.copy_probe:
+            a = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            del a, b
+            torch.cuda.empty_cache()
+        ctx.step(20)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.step(args.fixed_steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / args.fixed_steps
+        alg = float((152 * info[:, 0] + 4 * cells + 12 * info[:, 1]).sum())
+        print(json.dumps({"workload": f"{n} REV cubes, every cube active", "layout": layout, "block": block,
+                          "workgroups_per_sample": W0, "steps": args.fixed_steps, "ms_per_step": round(ms, 3),
+                          "cell_updates_per_s": round(float(cells.sum()) / (ms * 1e-3), 1),
+                          "algorithmic_bytes_per_step": alg,
+                          "algorithmic_gbs": round(alg / (ms * 1e-3) / 1e9, 1)}), flush=True)
+        return
     resident = 256 * 1024 // block  # workgroups of this size resident on 256 CUs at 4 waves per SIMD
     chunk = args.chunk
     prev = np.zeros(n, dtype=np.int64)
@@ -198,10 +226,11 @@ def rev_batch(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{n} periodic REV cubes, edge in {{32,48,64,96}}, porosity U[0.35,0.9], radii "
-                               f"U[3,10], TRT Lambda 3/16 tau 1.0, force 1e-6, CLI, AA, FP32 shifted, to steady "
+                               f"U[3,10], TRT Lambda 3/16 tau 1.0, force 1e-6, CLI, {layout}, FP32 shifted, to steady "
                                f"state (relative change <= 1e-7 per 100 steps)",
                    "samples": n, "cells": int(cells.sum()), "fluid_cells": int(info[:, 0].sum()),
-                   "links": int(info[:, 1].sum()), "block": block, "workgroups_per_sample": W0},
+                   "links": int(info[:, 1].sum()), "layout": layout, "block": block,
+                   "workgroups_per_sample": W0},
         "batch": {"wall_s": round(wall, 2), "converged": converged, "cell_updates": updates,
                   "steps_min": int(steps.min()), "steps_median": int(np.median(steps)),
                   "steps_max": int(steps.max()), "K_min": float(K.min()), "K_max": float(K.max())},
@@ -315,7 +344,8 @@ def main():
     ap.add_argument("--layout", choices=("aa", "twogrid", "brick"), default="brick",
                     help="bed: population layout of the sweep")
     ap.add_argument("--launch", default=None, metavar="BLOCK,FLAGS",
-                    help="bed: fixed launch shape instead of the autotuner (e.g. 1024,2)")
+                    help="fixed launch shape instead of the autotuner: bed BLOCK,FLAGS (e.g. 1024,2); "
+                         "rev-batch BLOCK,WORKGROUPS_PER_SAMPLE")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counter scaling)")
     ap.add_argument("--workload", choices=("bed", "rev-batch", "closure-kernels"), default="bed",
@@ -325,6 +355,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=2000, help="rev-batch: steps per persistent launch")
     ap.add_argument("--max-steps", type=int, default=2_000_000, help="rev-batch: cap per sample")
     ap.add_argument("--out", default=None, help="rev-batch: write per-sample K and profiles (JSON)")
+    ap.add_argument("--fixed-steps", type=int, default=0,
+                    help="rev-batch: time this many steps with every cube active (after 20 warm-up steps) "
+                         "instead of the run to steady state")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -440,7 +473,9 @@ def main():
         "fp32_rel_l2_vs_fp64_oracle": check,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg},
+                     "algorithmic_bytes_per_launch": alg,
+                     # counter bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) over this run's time per launch
+                     "traffic_gbs": round(traffic / (ms_per_step * 1e-3) / 1e9, 1) if traffic else None},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -150,8 +150,9 @@ void lbm_geometry_free(lbm_geometry* g);
  * lbm_required_bytes: size of the device buffer lbm_init needs for geometry g
  * and params p (populations, one partial bounce-back value per link, cell
  * info, link coefficients, reduction scratch).  With more than one domain the
- * batched layout is used (each domain has its own AA state; params.layout is
- * ignored). */
+ * batched kernel is used: each domain has its own state, in the brick layout
+ * (two grids) when params.layout is LBM_LAYOUT_BRICK, otherwise in the AA
+ * layout. */
 lbm_status lbm_required_bytes(const lbm_geometry* g, const lbm_params* p, int64_t* bytes);
 
 /* lbm_init: bind a context to the caller's device buffer dev_buf (at least

@@ -39,30 +39,37 @@ def batch_domains():
 
 
 PARAMS = W.Params(collision="trt", tau_plus=1.0, magic_lambda=3 / 16, force=(1e-5, 0.0, 0.0), layout="aa")
+LAYOUTS = ["aa", "brick"]  # AA in place, or 4x4x4 bricks with two grids per domain
 
 
-def test_batch_equals_single_domain_runs_bitwise():
-    say("test_batch_equals_single_domain_runs_bitwise")
+def params(layout):
+    return W.Params(**{**PARAMS.__dict__, "layout": layout})
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_equals_single_domain_runs_bitwise(layout):
+    say("test_batch_equals_single_domain_runs_bitwise", layout)
     lbm = _lbm()
     doms = batch_domains()
-    ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+    ctx = lbm.Context(lbm.Geometry(doms), params(layout))
     ctx.step(37)
     ctx.step(20)
     for i, d in enumerate(doms):
-        single = lbm.Context(lbm.Geometry(d), PARAMS)
+        single = lbm.Context(lbm.Geometry(d), params(layout))
         single.step(57)
         _, u1 = single.fields()
         _, u2 = ctx.fields(i)
         assert np.array_equal(u1, u2), i
 
 
-def test_batch_launch_shapes_bitwise():
-    say("test_batch_launch_shapes_bitwise")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_launch_shapes_bitwise(layout):
+    say("test_batch_launch_shapes_bitwise", layout)
     lbm = _lbm()
     doms = batch_domains()
     base = None
     for block, w in [(256, 1), (512, 2), (1024, 4), (256, 3), (512, 16)]:
-        ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+        ctx = lbm.Context(lbm.Geometry(doms), params(layout))
         ctx.batch_set_launch(block, w)
         steps = ctx.run_to_steady(rel_tol=1e-6, check_every=50, max_steps=3000)
         us = [ctx.fields(i)[1] for i in range(len(doms))]
@@ -73,11 +80,12 @@ def test_batch_launch_shapes_bitwise():
             assert np.array_equal(a, b), (block, w)
 
 
-def test_batch_fixed_steps_parity_with_oracle():
-    say("test_batch_fixed_steps_parity_with_oracle")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_fixed_steps_parity_with_oracle(layout):
+    say("test_batch_fixed_steps_parity_with_oracle", layout)
     lbm = _lbm()
     doms = batch_domains()[:4]
-    ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+    ctx = lbm.Context(lbm.Geometry(doms), params(layout))
     ctx.step(150)
     for i, d in enumerate(doms):
         ref = oracle.Sim(d, PARAMS)
@@ -89,14 +97,15 @@ def test_batch_fixed_steps_parity_with_oracle():
         assert e <= 1e-4
 
 
-def test_batch_run_to_steady_permeability():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_run_to_steady_permeability(layout):
     """Steady-state test (relative change of the mean velocity over
     check_every steps) and Darcy permeability (eq. (1)) per sample against
     the oracle run to its own steady state."""
-    say("test_batch_run_to_steady_permeability")
+    say("test_batch_run_to_steady_permeability", layout)
     lbm = _lbm()
     doms = [small_rev(0, 16), small_rev(1, 20), small_rev(2, 12)]
-    ctx = lbm.Context(lbm.Geometry(doms), PARAMS)
+    ctx = lbm.Context(lbm.Geometry(doms), params(layout))
     steps = ctx.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=200000)
     say("steps", steps)
     assert np.all(steps < 200000)
@@ -116,16 +125,17 @@ def test_batch_run_to_steady_permeability():
         assert abs(k / kref - 1) <= 2e-4
 
 
-def test_batch_restart_bitwise():
-    say("test_batch_restart_bitwise")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_restart_bitwise(layout):
+    say("test_batch_restart_bitwise", layout)
     lbm = _lbm()
     doms = batch_domains()[:3]
     g = lbm.Geometry(doms)
-    a = lbm.Context(g, PARAMS)
+    a = lbm.Context(g, params(layout))
     a.step(21)
     img = a.save()
     a.step(10)
-    b = lbm.Context(g, PARAMS)
+    b = lbm.Context(g, params(layout))
     b.load(img)
     b.step(10)
     for i in range(3):
@@ -164,16 +174,17 @@ def test_rev_workload_samples_permeability():
         assert abs(k / kref - 1) <= 1e-4
 
 
-def test_batch_steady_in_chunks_matches_one_call():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_steady_in_chunks_matches_one_call(layout):
     """run_to_steady in short launches (samples that converged earlier are
     skipped by the later launches) ends exactly where one long launch ends:
     same steps per sample, same fields bit for bit."""
-    say("test_batch_steady_in_chunks_matches_one_call")
+    say("test_batch_steady_in_chunks_matches_one_call", layout)
     lbm = _lbm()
     doms = batch_domains()
-    one = lbm.Context(lbm.Geometry(doms), PARAMS)
+    one = lbm.Context(lbm.Geometry(doms), params(layout))
     s1 = one.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=200000)
-    chunked = lbm.Context(lbm.Geometry(doms), PARAMS)
+    chunked = lbm.Context(lbm.Geometry(doms), params(layout))
     prev = np.zeros(len(doms), np.int64)
     for _ in range(2000):
         s2 = chunked.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=300)
@@ -185,3 +196,30 @@ def test_batch_steady_in_chunks_matches_one_call():
     assert np.array_equal(s1, s2)
     for i in range(len(doms)):
         assert np.array_equal(one.fields(i)[1], chunked.fields(i)[1]), i
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_rev_workload_representative_permeability(layout):
+    """Lowest- and highest-porosity cubes of the smallest (32) and largest (96)
+    edge of the batched REV workload, run to steady state together in one
+    batched launch; K against the oracle's steady permeability stored in
+    golden/rev_k.json (written by golden/make_rev_k.py) within 1e-4."""
+    import json
+    import os
+    say("test_rev_workload_representative_permeability", layout)
+    lbm = _lbm()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "rev_k.json")) as f:
+        gold = json.load(f)
+    assert len(gold) == 8 and {g["edge"] for g in gold} == {32, 96}
+    gen = [W.rev_sample_c3(g["index"]) for g in gold]
+    doms = [x[0] for x in gen]
+    p = W.Params(**{**gen[0][1].__dict__, "layout": layout})
+    ctx = lbm.Context(lbm.Geometry(doms), p)
+    steps = ctx.run_to_steady(rel_tol=1e-7, check_every=100, max_steps=400000)
+    say("steps", steps)
+    assert np.all(steps < 400000)
+    for i, g in enumerate(gold):
+        assert doms[i].nx == g["edge"] and abs(gen[i][3] - g["porosity"]) < 1e-12
+        k = ctx.permeability(i, 0)
+        say("sample", g["index"], "edge", g["edge"], "porosity", round(g["porosity"], 4), "K", k, "oracle", g["K"])
+        assert abs(k / g["K"] - 1) <= 1e-4, (g["index"], k, g["K"])
