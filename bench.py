@@ -107,9 +107,11 @@ def _gen_rev(i):
 
 def rev_batch(args):
     """512 periodic REV cubes (edge in {32,48,64,96}, porosity U[0.35,0.9],
-    radii U[3,10]) in one batched persistent launch per chunk of steps, to
-    steady state; the launch shape is autotuned once and the team size grows
-    as samples converge (every shape gives the same result bit for bit)."""
+    radii U[3,10]) to steady state in chunks of steps.  Brick layout: all
+    cubes in one brick array, one brick-sweep launch per step over the
+    running cubes; AA layout: one persistent launch per chunk, whose team
+    size grows as samples converge.  The launch shape is autotuned once
+    (every shape gives the same result bit for bit)."""
     import multiprocessing as mp
 
     import numpy as np
@@ -178,9 +180,11 @@ def rev_batch(args):
         prev = steps
         running = int((adv == chunk).sum())
         log(f"  {time.perf_counter() - t0:7.1f} s: {n - running} of {n} samples steady, "
-            f"steps up to {int(steps.max())}, team size {W}")
+            f"steps up to {int(steps.max())}" + ("" if layout == "brick" else f", team size {W}"))
         if running == 0 or steps.max() >= args.max_steps:
             break
+        if layout == "brick":
+            continue  # one launch per step over the running cubes' bricks: no teams to resize
         # fewer samples left: give each more workgroups (next power of two
         # of resident workgroups per running sample)
         want = 1 << max(0, int(np.ceil(np.log2(max(1.0, resident / running)))))

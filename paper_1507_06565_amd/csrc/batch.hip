@@ -1,11 +1,14 @@
 // Batched pore-scale runs: many independent small domains (REV samples of
 // uneven size) advanced by ONE persistent cooperative launch.
 //
+// (This file runs batches in the AA layout; batches in the brick layout are
+// stepped by the brick sweep itself over one brick array that holds every
+// domain, brick_batch.cpp.)
+//
 // The grid holds as many workgroups as can be resident at once.  They form
 // teams of W consecutive workgroups; a team pops the next domain from a
 // largest-first queue (one atomic counter), steps it with the same per-cell
-// update as the single-domain sweep (cell.hpp; the AA layout, or the brick
-// layout with two grids per domain and one wavefront per brick), synchronising its
+// update as the single-domain sweep (AA layout, cell.hpp), synchronising its
 // W workgroups after every time step with a counter barrier, and every
 // `check_every` steps evaluates the steady-state test on the FP64 mean
 // x-velocity of the domain.  When the domain converges (or reaches its step
@@ -40,13 +43,9 @@ struct BatchDom {
     const uint32_t* info;
     const int32_t* segbase;
     const float* lparam;
-    float* pv;        // partial bounce-back values, one per link (of grid 0 in the brick layout)
-    double* partial;  // one FP64 partial sum per 64-cell chunk (per brick in the brick layout)
+    float* pv;        // partial bounce-back values, one per link
+    double* partial;  // one FP64 partial sum per 64-cell chunk
     int32_t nx, ny, nz, ncells;
-    // brick layout: grid 1 starts `grid` floats after grid 0; 27 neighbours per stored brick
-    int64_t grid;
-    const int32_t* nbr;
-    int32_t nbricks;
 };
 
 struct BatchArgs {
@@ -112,7 +111,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int BC, int BLOCK, bool BRK>
+template <int BC, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
     __shared__ int s_ok, s_dom, s_stop;
     const int W = a.W;
@@ -145,10 +144,7 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
         const float* lparam = uniform_ptr(D->lparam);
         float* pv = uniform_ptr(D->pv);
         double* partial = uniform_ptr(D->partial);
-        const int nbricks = BRK ? __builtin_amdgcn_readfirstlane(D->nbricks) : 0;
-        const int32_t* nbr = BRK ? uniform_ptr(D->nbr) : nullptr;
-        const int64_t gridf = BRK ? D->grid : 0;
-        const int nchunk = BRK ? nbricks : ((N + 63) >> 6);
+        const int nchunk = (N + 63) >> 6;
         const int64_t s0 = a.steps[d];
         int64_t s = s0;
         bool done = a.steady ? (a.status[d] != 0) : false;
@@ -156,28 +152,6 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
         while (!done) {
             const bool check = a.steady && ((s + 1 - s0) % a.check_every == 0);
             const bool even = (s & 1) == 0;
-            if (BRK) {
-                // two grids: step s reads grid (s & 1) and writes the other
-                constexpr int NW = BLOCK / 64;
-                const int cur = (int)(s & 1);
-                const PopStrided src{pa.base + cur * gridf, pa.stride};
-                const PopStrided dst{pa.base + (1 - cur) * gridf, pa.stride};
-                const float* pva = src.base + (int64_t)Q * pa.stride;
-                float* pvb = dst.base + (int64_t)Q * pa.stride;
-                const int wave = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
-                for (int tile = rank; tile * NW < nbricks; tile += W) {
-                    const int brick = tile * NW + wave;  // uniform per wavefront
-                    if (brick < nbricks) {
-                        const BrickNb nbi(nbr[(int64_t)brick * 27 + (l < 27 ? l : 13)], brick, l);
-                        const float ux = cell_update<L_TWOGRID, P_EVEN, BC, false, true>(
-                            src, dst, info, segbase, lparam, pva, pvb, a.k, nbi, brick * 64 + l);
-                        if (check) {
-                            const double w = wave_sum((double)ux);
-                            if (l == 0) partial[brick] = w;
-                        }
-                    }
-                }
-            } else
             for (int tile = rank; tile * BLOCK < N; tile += W) {
                 const int c = tile * BLOCK + threadIdx.x;
                 float ux = 0.0f;
@@ -230,50 +204,36 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
     }
 }
 
-template <int BC, int BLOCK, bool BRK>
+template <int BC, int BLOCK>
 hipError_t launch_batch(const BatchArgs& args, int grid, hipStream_t s) {
     BatchArgs a = args;
     void* params[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch<BC, BLOCK, BRK>), dim3(grid),
-                                      dim3(BLOCK), params, 0, s);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch<BC, BLOCK>), dim3(grid), dim3(BLOCK),
+                                      params, 0, s);
 }
 
-template <int BC, int BLOCK, bool BRK>
+template <int BC, int BLOCK>
 int max_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_batch<BC, BLOCK, BRK>),
-                                                     BLOCK, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_batch<BC, BLOCK>), BLOCK,
+                                                     0) != hipSuccess)
         return 0;
     return nb;
-}
-
-template <bool BRK>
-int blocks_per_cu(int bc, int block) {
-    switch (block) {
-        case 256: return bc == LBM_BC_SBB ? max_blocks_per_cu<LBM_BC_SBB, 256, BRK>() : bc == LBM_BC_CLI ? max_blocks_per_cu<LBM_BC_CLI, 256, BRK>() : max_blocks_per_cu<LBM_BC_BOUZIDI, 256, BRK>();
-        case 512: return bc == LBM_BC_SBB ? max_blocks_per_cu<LBM_BC_SBB, 512, BRK>() : bc == LBM_BC_CLI ? max_blocks_per_cu<LBM_BC_CLI, 512, BRK>() : max_blocks_per_cu<LBM_BC_BOUZIDI, 512, BRK>();
-        case 1024: return bc == LBM_BC_SBB ? max_blocks_per_cu<LBM_BC_SBB, 1024, BRK>() : bc == LBM_BC_CLI ? max_blocks_per_cu<LBM_BC_CLI, 1024, BRK>() : max_blocks_per_cu<LBM_BC_BOUZIDI, 1024, BRK>();
-    }
-    return -1;
 }
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct DomPlan {
     int64_t N, stride, nl, nchunk, nseed;
-    int64_t NS, nbricks, nbmap;  // stored cells; brick layout: stored bricks, brick-map entries
     int64_t grid;  // floats of the state block: Q population arrays + partial values
-    int64_t off_pop, off_info, off_segbase, off_lparam, off_partial, off_seed, off_nbr, off_bmap;
+    int64_t off_pop, off_info, off_segbase, off_lparam, off_partial, off_seed;
 };
 
 struct TuneKey {
     std::string arch;
     int ndom;
     int64_t cells;
-    bool brick;
-    bool operator<(const TuneKey& o) const {
-        return std::tie(arch, ndom, cells, brick) < std::tie(o.arch, o.ndom, o.cells, o.brick);
-    }
+    bool operator<(const TuneKey& o) const { return std::tie(arch, ndom, cells) < std::tie(o.arch, o.ndom, o.cells); }
 };
 std::mutex g_mu;
 std::map<TuneKey, std::pair<int, int>> g_cache;
@@ -298,12 +258,7 @@ struct BatchCtx {
     std::string arch;
     int cus = 0;
     int block = 512, W = 4;
-    bool brick = false;  // brick layout (two grids per domain)
-    int64_t cells() const {
-        int64_t n = 0;
-        for (auto& P : plans) n += P.N;
-        return n;
-    }
+    BrickBatch* flat = nullptr;  // brick layout: every call goes to brick_batch.cpp
 };
 
 namespace {
@@ -315,28 +270,17 @@ lbm_status plan(const std::vector<DomainGeo>& doms, const lbm_params& p, BatchCt
     int64_t o = 0;
     b.plans.clear();
     b.desc.clear();
-    b.brick = p.layout == LBM_LAYOUT_BRICK;
     for (const auto& G : doms) {
         const auto& d = G.desc;
-        if (b.brick && !brick_dims_ok(d))
-            return set_error(LBM_E_INVAL, "brick layout needs nx, ny, nz divisible by 4 in every domain");
         if (d.bc != d0.bc) return set_error(LBM_E_INVAL, "all domains of a batch must use the same boundary scheme");
         for (int a = 0; a < 3; ++a)
             if (d.wall_hi_velocity[a] != d0.wall_hi_velocity[a])
                 return set_error(LBM_E_INVAL, "all domains of a batch must share the wall velocity");
         DomPlan P{};
         P.N = G.ncells();
-        P.NS = P.N;
-        if (b.brick) {
-            BrickMap bm;
-            build_brick_map(G, bm, false);
-            P.nbricks = bm.nstored;
-            P.nbmap = (int64_t)bm.bx * bm.by * bm.bz;
-            P.NS = P.nbricks * 64;
-        }
-        P.stride = align_up(P.NS, 64) + 64;
+        P.stride = align_up(P.N, 64) + 64;
         P.nl = (int64_t)G.lcell.size();
-        P.nchunk = b.brick ? P.nbricks : (P.N + 63) / 64;
+        P.nchunk = (P.N + 63) / 64;
         P.nseed = 0;
         const bool moving = d.wall_hi_velocity[0] != 0.0 || d.wall_hi_velocity[1] != 0.0 || d.wall_hi_velocity[2] != 0.0;
         if (moving)
@@ -345,14 +289,12 @@ lbm_status plan(const std::vector<DomainGeo>& doms, const lbm_params& p, BatchCt
         P.grid = Q * P.stride + align_up(P.nl + Q, 64);
         if (P.grid * 4 >= ((int64_t)1 << 32))
             return set_error(LBM_E_INVAL, "a batched domain's state must stay below 4 GiB (fewer than ~50 M cells)");
-        P.off_pop = o; o = align_up(o + (b.brick ? 2 : 1) * P.grid * 4, 256);
-        P.off_info = o; o = align_up(o + P.NS * 4, 256);
-        P.off_segbase = o; o = align_up(o + ((P.NS >> SEG_SHIFT) + 1) * 4, 256);
+        P.off_pop = o; o = align_up(o + P.grid * 4, 256);
+        P.off_info = o; o = align_up(o + P.N * 4, 256);
+        P.off_segbase = o; o = align_up(o + ((P.N >> SEG_SHIFT) + 1) * 4, 256);
         P.off_lparam = o; o = align_up(o + (P.nl + Q) * 4, 256);
-        P.off_partial = o; o = align_up(o + std::max<int64_t>(P.nchunk, 1) * 8, 256);
+        P.off_partial = o; o = align_up(o + P.nchunk * 8, 256);
         P.off_seed = o; o = align_up(o + std::max<int64_t>(P.nseed, 1) * 12, 256);
-        P.off_nbr = o; o = align_up(o + P.nbricks * 27 * 4, 256);
-        P.off_bmap = o; o = align_up(o + P.nbmap * 4, 256);
         b.plans.push_back(P);
         b.desc.push_back(d);
         b.max_np = std::max<int64_t>(b.max_np, std::max(d.nx, std::max(d.ny, d.nz)));
@@ -389,7 +331,7 @@ lbm_status reset(BatchCtx* b) {
     for (int d = 0; d < b->ndom; ++d) {
         const DomPlan& P = b->plans[d];
         float* pop = reinterpret_cast<float*>(b->buf + P.off_pop);
-        HIPCHK(launch_fill_zero(pop, (b->brick ? 2 : 1) * P.grid, b->stream), "zero populations");
+        HIPCHK(launch_fill_zero(pop, P.grid, b->stream), "zero populations");
         if (P.nseed > 0)
             HIPCHK(launch_scatter(pop, reinterpret_cast<const int64_t*>(b->buf + P.off_seed),
                                   reinterpret_cast<const float*>(b->buf + P.off_seed + P.nseed * 8), P.nseed,
@@ -409,8 +351,13 @@ lbm_status reset(BatchCtx* b) {
 
 // one persistent launch; steady = 0 runs exactly n steps on every domain
 lbm_status run(BatchCtx* b, int steady, double tol, int64_t check_every, int64_t n, int block, int W) {
-    const int per_cu = b->brick ? blocks_per_cu<true>(b->bc, block) : blocks_per_cu<false>(b->bc, block);
-    if (per_cu < 0) return set_error(LBM_E_INVAL, "batched workgroup size must be 256, 512 or 1024");
+    int per_cu = 0;
+    switch (block) {
+        case 256: per_cu = b->bc == LBM_BC_SBB ? max_blocks_per_cu<LBM_BC_SBB, 256>() : b->bc == LBM_BC_CLI ? max_blocks_per_cu<LBM_BC_CLI, 256>() : max_blocks_per_cu<LBM_BC_BOUZIDI, 256>(); break;
+        case 512: per_cu = b->bc == LBM_BC_SBB ? max_blocks_per_cu<LBM_BC_SBB, 512>() : b->bc == LBM_BC_CLI ? max_blocks_per_cu<LBM_BC_CLI, 512>() : max_blocks_per_cu<LBM_BC_BOUZIDI, 512>(); break;
+        case 1024: per_cu = b->bc == LBM_BC_SBB ? max_blocks_per_cu<LBM_BC_SBB, 1024>() : b->bc == LBM_BC_CLI ? max_blocks_per_cu<LBM_BC_CLI, 1024>() : max_blocks_per_cu<LBM_BC_BOUZIDI, 1024>(); break;
+        default: return set_error(LBM_E_INVAL, "batched workgroup size must be 256, 512 or 1024");
+    }
     if (per_cu < 1) return set_error(LBM_E_DEVICE, "batched kernel cannot be resident");
     int64_t grid = (int64_t)per_cu * b->cus;
     grid = grid / W * W;
@@ -420,7 +367,7 @@ lbm_status run(BatchCtx* b, int steady, double tol, int64_t check_every, int64_t
     std::vector<int32_t> order(b->ndom);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return b->plans[x].NS > b->plans[y].NS; });
+                     [&](int x, int y) { return b->plans[x].N > b->plans[y].N; });
     HIPCHK(hipMemcpyAsync(b->buf + b->off_order, order.data(), b->ndom * 4, hipMemcpyHostToDevice, b->stream),
            "queue order");
     HIPCHK(hipMemsetAsync(b->buf + b->off_queue, 0, 4, b->stream), "reset queue");
@@ -445,21 +392,15 @@ lbm_status run(BatchCtx* b, int steady, double tol, int64_t check_every, int64_t
     a.W = W;
     a.spin_limit = 1 << 22;
     hipError_t e = hipSuccess;
-#define BL(BC, BRK)                                                              \
-    switch (block) {                                                             \
-        case 256: e = launch_batch<BC, 256, BRK>(a, (int)grid, b->stream); break;  \
-        case 512: e = launch_batch<BC, 512, BRK>(a, (int)grid, b->stream); break;  \
-        default: e = launch_batch<BC, 1024, BRK>(a, (int)grid, b->stream); break; \
+#define BL(BC)                                                              \
+    switch (block) {                                                        \
+        case 256: e = launch_batch<BC, 256>(a, (int)grid, b->stream); break;  \
+        case 512: e = launch_batch<BC, 512>(a, (int)grid, b->stream); break;  \
+        default: e = launch_batch<BC, 1024>(a, (int)grid, b->stream); break; \
     }
-    if (b->brick) {
-        if (b->bc == LBM_BC_SBB) { BL(LBM_BC_SBB, true) }
-        else if (b->bc == LBM_BC_CLI) { BL(LBM_BC_CLI, true) }
-        else { BL(LBM_BC_BOUZIDI, true) }
-    } else {
-        if (b->bc == LBM_BC_SBB) { BL(LBM_BC_SBB, false) }
-        else if (b->bc == LBM_BC_CLI) { BL(LBM_BC_CLI, false) }
-        else { BL(LBM_BC_BOUZIDI, false) }
-    }
+    if (b->bc == LBM_BC_SBB) { BL(LBM_BC_SBB) }
+    else if (b->bc == LBM_BC_CLI) { BL(LBM_BC_CLI) }
+    else { BL(LBM_BC_BOUZIDI) }
 #undef BL
     HIPCHK(e, "persistent batched launch");
     int32_t err = 0;
@@ -476,12 +417,11 @@ lbm_status run(BatchCtx* b, int steady, double tol, int64_t check_every, int64_t
 MomentArgs dom_moments(BatchCtx* b, int d) {
     const DomPlan& P = b->plans[d];
     MomentArgs m{};
-    m.A = reinterpret_cast<const float*>(b->buf + P.off_pop) + (b->brick ? (b->steps[d] & 1) * P.grid : 0);
+    m.A = reinterpret_cast<const float*>(b->buf + P.off_pop);
     m.stride = P.stride;
     m.info = reinterpret_cast<const uint32_t*>(b->buf + P.off_info);
-    m.bmap = b->brick ? reinterpret_cast<const int32_t*>(b->buf + P.off_bmap) : nullptr;
     m.nx = b->desc[d].nx; m.ny = b->desc[d].ny; m.nz = b->desc[d].nz;
-    m.layout = b->brick ? L_BRICK : L_AA;
+    m.layout = L_AA;
     m.parity = b->steps[d] == 0 ? -1 : ((b->steps[d] - 1) % 2 == 0 ? P_EVEN : P_ODD);
     m.rho0 = b->p.rho0;
     for (int a = 0; a < 3; ++a) m.F[a] = b->p.force[a];
@@ -502,6 +442,7 @@ lbm_status dom_plane_sums(BatchCtx* b, int d, int axis, std::vector<double>& out
 }  // namespace
 
 lbm_status batch_required_bytes(const std::vector<DomainGeo>& doms, const lbm_params& p, int64_t* bytes) {
+    if (p.layout == LBM_LAYOUT_BRICK) return bbatch_required_bytes(doms, p, bytes);
     BatchCtx b;
     lbm_status s = plan(doms, p, b);
     if (s != LBM_OK) return s;
@@ -511,6 +452,15 @@ lbm_status batch_required_bytes(const std::vector<DomainGeo>& doms, const lbm_pa
 
 lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, double wp, double wm, char* buf,
                       int64_t bytes, hipStream_t s, BatchCtx** out) {
+    if (p.layout == LBM_LAYOUT_BRICK) {
+        BrickBatch* f = nullptr;
+        lbm_status st = bbatch_init(doms, p, wp, wm, buf, bytes, s, &f);
+        if (st != LBM_OK) return st;
+        auto* b = new BatchCtx;
+        b->flat = f;
+        *out = b;
+        return LBM_OK;
+    }
     auto* b = new BatchCtx;
     lbm_status st = plan(doms, p, *b);
     if (st != LBM_OK) { delete b; return st; }
@@ -535,9 +485,7 @@ lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, d
         const DomPlan& P = b->plans[d];
         DeviceImages im;
         std::string err;
-        BrickMap bm;
-        if (b->brick) build_brick_map(doms[d], bm, true);
-        st = build_images(doms[d], b->brick ? LBM_LAYOUT_BRICK : LBM_LAYOUT_AA, bm, P.stride, b->k, im, err);
+        st = build_images(doms[d], LBM_LAYOUT_AA, BrickMap{}, P.stride, b->k, im, err);
         if (st != LBM_OK) { delete b; return set_error(st, err); }
         BatchDom& T = table[d];
         for (int k = 0; k < Q; ++k) T.pa[k] = reinterpret_cast<float*>(buf + P.off_pop) + k * P.stride;
@@ -548,16 +496,7 @@ lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, d
         T.pv = reinterpret_cast<float*>(buf + P.off_pop) + Q * P.stride;
         T.partial = reinterpret_cast<double*>(buf + P.off_partial);
         T.nx = doms[d].desc.nx; T.ny = doms[d].desc.ny; T.nz = doms[d].desc.nz; T.ncells = (int32_t)P.N;
-        T.grid = P.grid;
-        T.nbr = reinterpret_cast<const int32_t*>(buf + P.off_nbr);
-        T.nbricks = (int32_t)P.nbricks;
-        hipError_t e = hipSuccess;
-        if (!im.info.empty())
-            e = hipMemcpyAsync(buf + P.off_info, im.info.data(), im.info.size() * 4, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && !bm.nbr.empty())
-            e = hipMemcpyAsync(buf + P.off_nbr, bm.nbr.data(), bm.nbr.size() * 4, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && !bm.id.empty())
-            e = hipMemcpyAsync(buf + P.off_bmap, bm.id.data(), bm.id.size() * 4, hipMemcpyHostToDevice, s);
+        hipError_t e = hipMemcpyAsync(buf + P.off_info, im.info.data(), im.info.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(buf + P.off_segbase, im.segbase.data(), im.segbase.size() * 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
@@ -581,7 +520,9 @@ lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, d
     }
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_cache.find({b->arch, b->ndom, b->cells(), b->brick});
+        int64_t cells = 0;
+        for (auto& P : b->plans) cells += P.N;
+        auto it = g_cache.find({b->arch, b->ndom, cells});
         if (it != g_cache.end()) { b->block = it->second.first; b->W = it->second.second; }
     }
     st = reset(b);
@@ -591,12 +532,14 @@ lbm_status batch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, d
 }
 
 lbm_status batch_step(BatchCtx* b, int64_t n) {
+    if (b->flat) return bbatch_step(b->flat, n);
     if (n == 0) return LBM_OK;
     return run(b, 0, 0.0, 1, n, b->block, b->W);
 }
 
 lbm_status batch_run_to_steady(BatchCtx* b, double rel_tol, int64_t check_every, int64_t max_steps,
                                int64_t* steps_done) {
+    if (b->flat) return bbatch_run_to_steady(b->flat, rel_tol, check_every, max_steps, steps_done);
     lbm_status s = run(b, 1, rel_tol, check_every, max_steps, b->block, b->W);
     if (s != LBM_OK) return s;
     for (int d = 0; d < b->ndom; ++d) steps_done[d] = b->steps[d];
@@ -606,6 +549,7 @@ lbm_status batch_run_to_steady(BatchCtx* b, double rel_tol, int64_t check_every,
 }
 
 lbm_status batch_profile(BatchCtx* b, int dom, int axis, int comp, double* u_sup, double* u_int, double* por) {
+    if (b->flat) return bbatch_profile(b->flat, dom, axis, comp, u_sup, u_int, por);
     std::vector<double> ps;
     lbm_status s = dom_plane_sums(b, dom, axis, ps);
     if (s != LBM_OK) return s;
@@ -622,6 +566,7 @@ lbm_status batch_profile(BatchCtx* b, int dom, int axis, int comp, double* u_sup
 }
 
 lbm_status batch_permeability(BatchCtx* b, int dom, int fa, int z0, int z1, double* k) {
+    if (b->flat) return bbatch_permeability(b->flat, dom, fa, z0, z1, k);
     const auto& D = b->desc[dom];
     if (z0 < 0 || z1 > D.nz || z0 >= z1) return set_error(LBM_E_INVAL, "bad plane range");
     if (b->p.force[fa] == 0.0) return set_error(LBM_E_INVAL, "no body force along the flow axis");
@@ -636,6 +581,7 @@ lbm_status batch_permeability(BatchCtx* b, int dom, int fa, int z0, int z1, doub
 }
 
 lbm_status batch_fields(BatchCtx* b, int dom, double* rho, double* u) {
+    if (b->flat) return bbatch_fields(b->flat, dom, rho, u);
     const int64_t N = b->plans[dom].N, chunk = b->chunk;
     double* dv = reinterpret_cast<double*>(b->buf + b->off_fields);
     std::vector<double> h((size_t)chunk * 4);
@@ -653,6 +599,7 @@ lbm_status batch_fields(BatchCtx* b, int dom, double* rho, double* u) {
 }
 
 lbm_status batch_totals(BatchCtx* b, int dom, double* mass, double* mom) {
+    if (b->flat) return bbatch_totals(b->flat, dom, mass, mom);
     std::vector<double> ps;
     lbm_status s = dom_plane_sums(b, dom, 2, ps);
     if (s != LBM_OK) return s;
@@ -674,6 +621,7 @@ lbm_status batch_totals(BatchCtx* b, int dom, double* mass, double* mom) {
 static const int64_t kBatchMagic = 0x4c424d4241544348;  // "LBMBATCH"
 
 lbm_status batch_state_bytes(BatchCtx* b, int64_t* bytes) {
+    if (b->flat) return bbatch_state_bytes(b->flat, bytes);
     int64_t n = 32;
     for (auto& P : b->plans) n += 24 + P.grid * 4;
     *bytes = n;
@@ -681,6 +629,7 @@ lbm_status batch_state_bytes(BatchCtx* b, int64_t* bytes) {
 }
 
 lbm_status batch_save(BatchCtx* b, void* host, int64_t bytes, int64_t steps) {
+    if (b->flat) return bbatch_save(b->flat, host, bytes, steps);
     (void)bytes;
     int64_t* h = reinterpret_cast<int64_t*>(host);
     h[0] = kBatchMagic; h[1] = steps; h[2] = b->ndom; h[3] = 0;
@@ -694,9 +643,7 @@ lbm_status batch_save(BatchCtx* b, void* host, int64_t bytes, int64_t steps) {
         std::memcpy(&meta[2], &up[d], 8);
         std::memcpy(o, meta, 24);
         o += 24;
-        const int64_t cur = b->brick ? (b->steps[d] & 1) : 0;  // the grid that holds the state
-        HIPCHK(hipMemcpyAsync(o, b->buf + P.off_pop + cur * P.grid * 4, P.grid * 4, hipMemcpyDeviceToHost, b->stream),
-               "save");
+        HIPCHK(hipMemcpyAsync(o, b->buf + P.off_pop, P.grid * 4, hipMemcpyDeviceToHost, b->stream), "save");
         o += P.grid * 4;
     }
     HIPCHK(hipStreamSynchronize(b->stream), "synchronise");
@@ -704,6 +651,7 @@ lbm_status batch_save(BatchCtx* b, void* host, int64_t bytes, int64_t steps) {
 }
 
 lbm_status batch_load(BatchCtx* b, const void* host, int64_t bytes) {
+    if (b->flat) return bbatch_load(b->flat, host, bytes);
     (void)bytes;
     const int64_t* h = reinterpret_cast<const int64_t*>(host);
     if (h[0] != kBatchMagic || h[2] != b->ndom) return set_error(LBM_E_INVAL, "not a state image of this batch");
@@ -717,9 +665,7 @@ lbm_status batch_load(BatchCtx* b, const void* host, int64_t bytes) {
         b->steps[d] = meta[0];
         b->status[d] = (int32_t)meta[1];
         std::memcpy(&up[d], &meta[2], 8);
-        const int64_t cur = b->brick ? (b->steps[d] & 1) : 0;
-        HIPCHK(hipMemcpyAsync(b->buf + P.off_pop + cur * P.grid * 4, o, P.grid * 4, hipMemcpyHostToDevice, b->stream),
-               "load");
+        HIPCHK(hipMemcpyAsync(b->buf + P.off_pop, o, P.grid * 4, hipMemcpyHostToDevice, b->stream), "load");
         o += P.grid * 4;
     }
     HIPCHK(hipMemcpyAsync(b->buf + b->off_steps, b->steps.data(), b->ndom * 8, hipMemcpyHostToDevice, b->stream),
@@ -732,6 +678,7 @@ lbm_status batch_load(BatchCtx* b, const void* host, int64_t bytes) {
 }
 
 lbm_status batch_autotune(BatchCtx* b, int32_t steps_per_trial) {
+    if (b->flat) return bbatch_autotune(b->flat, steps_per_trial);
     for (int d = 0; d < b->ndom; ++d)
         if (b->steps[d] != 0) return set_error(LBM_E_STATE, "autotune a batch before stepping it");
     hipEvent_t e0, e1;
@@ -761,11 +708,14 @@ lbm_status batch_autotune(BatchCtx* b, int32_t steps_per_trial) {
     b->block = bb;
     b->W = bw;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[{b->arch, b->ndom, b->cells(), b->brick}] = {bb, bw};
+    int64_t cells = 0;
+    for (auto& P : b->plans) cells += P.N;
+    g_cache[{b->arch, b->ndom, cells}] = {bb, bw};
     return LBM_OK;
 }
 
 lbm_status batch_set_launch(BatchCtx* b, int32_t block, int32_t W) {
+    if (b->flat) return bbatch_set_launch(b->flat, block, W);
     if (block != 256 && block != 512 && block != 1024) return set_error(LBM_E_INVAL, "block must be 256, 512 or 1024");
     if (W < 1 || W > 64) return set_error(LBM_E_INVAL, "workgroups per domain must be in [1, 64]");
     b->block = block;
@@ -774,11 +724,15 @@ lbm_status batch_set_launch(BatchCtx* b, int32_t block, int32_t W) {
 }
 
 lbm_status batch_get_launch(BatchCtx* b, int32_t* block, int32_t* W) {
+    if (b->flat) return bbatch_get_launch(b->flat, block, W);
     if (block) *block = b->block;
     if (W) *W = b->W;
     return LBM_OK;
 }
 
-void batch_destroy(BatchCtx* b) { delete b; }
+void batch_destroy(BatchCtx* b) {
+    if (b && b->flat) bbatch_destroy(b->flat);
+    delete b;
+}
 
 }  // namespace lbm

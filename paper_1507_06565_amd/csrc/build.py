@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["sweep.hip", "reduce.hip", "batch.hip", "gray.hip", "mlp.hip"]
-HOST_SOURCES = ["geometry.cpp", "images.cpp", "capi.cpp"]
+HOST_SOURCES = ["geometry.cpp", "images.cpp", "capi.cpp", "brick_batch.cpp"]
 
 
 def _hipcc():

@@ -80,7 +80,9 @@ struct SweepArgs {
     float* pvb;           // ... and written for the next step (AA: pva == pvb)
     int32_t nx, ny, nz, ncells;
     const int32_t* nbr;   // brick layout: 27 neighbour bricks per stored brick
-    int32_t nbricks;      // brick layout: stored bricks
+    int32_t nbricks;      // brick layout: bricks to update (entries of `list` when it is set)
+    const int32_t* list;  // brick layout, batches: the bricks to update (null: 0 .. nbricks-1)
+    double* partial;      // brick layout, batches: per-brick FP64 sum of u_x written on check steps
     CellConsts k;
     int32_t xcd_remap;
     int32_t nt;           // non-temporal hints on the aligned streams
@@ -116,6 +118,16 @@ lbm_status build_images(const DomainGeo& G, int layout, const BrickMap& bm, int6
 CellConsts make_consts(const lbm_params& p, double wp, double wm, const double* wall_velocity);
 
 hipError_t launch_sweep(const SweepArgs& a, int layout, int parity, int bc, int block, hipStream_t s);
+
+// brick sweep over a.list (a.nbricks entries); with check, every updated
+// brick's wavefront also stores the fixed-order FP64 sum of its cells' u_x
+// in a.partial[brick]
+hipError_t launch_sweep_bricks(const SweepArgs& a, int bc, int block, bool check, hipStream_t s);
+
+// out[d] = sum of partial[first[d] .. first[d] + count[d]) in a fixed order
+// (one wavefront per domain), for the domains listed in doms[0 .. n)
+hipError_t launch_domain_sums(const double* partial, const int32_t* first, const int32_t* count, const int32_t* doms,
+                              int n, double* out, hipStream_t s);
 
 struct MomentArgs {
     const float* A;

@@ -47,17 +47,41 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepArgs a) {
 
 // Brick layout: one wavefront per stored brick, lane l = cell l of the brick
 // (lx + 4 ly + 16 lz); the pull goes through the brick's neighbour table and
-// the store is aligned, as in the two-grid layout.
-template <int BC, int BLOCK, bool NT>
+// the store is aligned, as in the two-grid layout.  LIST: the bricks come
+// from a.list (a batch of domains stored as one brick array, each domain's
+// neighbour table wrapping onto itself); CHECK: the wavefront also stores the
+// sum of its cells' u_x (fixed butterfly) for the steady-state test.
+template <int BC, int BLOCK, bool NT, bool LIST, bool CHECK>
 __global__ void __launch_bounds__(BLOCK) k_sweep_brick(SweepArgs a) {
     int b = blockIdx.x;
     if (a.xcd_remap) b = remap_block(b, gridDim.x);
-    const int brick = b * (BLOCK / 64) + (int)(threadIdx.x >> 6);  // uniform per wavefront
-    if (brick >= a.nbricks) return;
+    const int slot = b * (BLOCK / 64) + (int)(threadIdx.x >> 6);  // uniform per wavefront
+    if (slot >= a.nbricks) return;
+    const int brick = LIST ? __builtin_amdgcn_readfirstlane(a.list[slot]) : slot;
     const int l = threadIdx.x & 63;
     const BrickNb nbi(a.nbr[(int64_t)brick * 27 + (l < 27 ? l : 13)], brick, l);
-    (void)cell_update<L_TWOGRID, P_EVEN, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, a.info, a.segbase,
-                                                        a.lparam, a.pva, a.pvb, a.k, nbi, brick * 64 + l);
+    const float ux = cell_update<L_TWOGRID, P_EVEN, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, a.info,
+                                                                   a.segbase, a.lparam, a.pva, a.pvb, a.k, nbi,
+                                                                   brick * 64 + l);
+    if (CHECK) {
+        double v = (double)ux;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (l == 0) a.partial[brick] = v;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_domain_sums(const double* __restrict__ partial,
+                                                    const int32_t* __restrict__ first,
+                                                    const int32_t* __restrict__ count,
+                                                    const int32_t* __restrict__ doms, double* __restrict__ out) {
+    const int d = doms[blockIdx.x];
+    const int f = first[d], n = count[d];
+    double v = 0.0;
+    for (int i = (int)threadIdx.x; i < n; i += 64) v += partial[f + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (threadIdx.x == 0) out[d] = v;
 }
 
 template <int LAYOUT, int PARITY, int BC, int BLOCK>
@@ -66,9 +90,9 @@ hipError_t launch4(const SweepArgs& a, hipStream_t s) {
         const unsigned nb = (unsigned)(((int64_t)a.nbricks + BLOCK / 64 - 1) / (BLOCK / 64));
         if (nb == 0) return hipSuccess;
         if (a.nt)
-            k_sweep_brick<BC, BLOCK, true><<<nb, BLOCK, 0, s>>>(a);
+            k_sweep_brick<BC, BLOCK, true, false, false><<<nb, BLOCK, 0, s>>>(a);
         else
-            k_sweep_brick<BC, BLOCK, false><<<nb, BLOCK, 0, s>>>(a);
+            k_sweep_brick<BC, BLOCK, false, false, false><<<nb, BLOCK, 0, s>>>(a);
         return hipGetLastError();
     } else {
         const unsigned nb = (unsigned)(((int64_t)a.ncells + BLOCK - 1) / BLOCK);
@@ -123,6 +147,48 @@ __global__ void k_scatter(float* p, const int64_t* idx, const float* val, int64_
 hipError_t launch_scatter(float* p, const int64_t* idx, const float* val, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_scatter<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, idx, val, n);
+    return hipGetLastError();
+}
+
+template <int BC, int BLOCK>
+hipError_t launch_list(const SweepArgs& a, bool check, hipStream_t s) {
+    const unsigned nb = (unsigned)(((int64_t)a.nbricks + BLOCK / 64 - 1) / (BLOCK / 64));
+    if (nb == 0) return hipSuccess;
+    if (a.nt) {
+        if (check) k_sweep_brick<BC, BLOCK, true, true, true><<<nb, BLOCK, 0, s>>>(a);
+        else k_sweep_brick<BC, BLOCK, true, true, false><<<nb, BLOCK, 0, s>>>(a);
+    } else {
+        if (check) k_sweep_brick<BC, BLOCK, false, true, true><<<nb, BLOCK, 0, s>>>(a);
+        else k_sweep_brick<BC, BLOCK, false, true, false><<<nb, BLOCK, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <int BC>
+hipError_t launch_list_bc(const SweepArgs& a, int block, bool check, hipStream_t s) {
+    switch (block) {
+        case 64: return launch_list<BC, 64>(a, check, s);
+        case 128: return launch_list<BC, 128>(a, check, s);
+        case 256: return launch_list<BC, 256>(a, check, s);
+        case 512: return launch_list<BC, 512>(a, check, s);
+        case 1024: return launch_list<BC, 1024>(a, check, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_bricks(const SweepArgs& a, int bc, int block, bool check, hipStream_t s) {
+    switch (bc) {
+        case LBM_BC_SBB: return launch_list_bc<LBM_BC_SBB>(a, block, check, s);
+        case LBM_BC_CLI: return launch_list_bc<LBM_BC_CLI>(a, block, check, s);
+        case LBM_BC_BOUZIDI: return launch_list_bc<LBM_BC_BOUZIDI>(a, block, check, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_domain_sums(const double* partial, const int32_t* first, const int32_t* count, const int32_t* doms,
+                              int n, double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_domain_sums<<<(unsigned)n, 64, 0, s>>>(partial, first, count, doms, out);
     return hipGetLastError();
 }
 
