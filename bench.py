@@ -119,8 +119,15 @@ def rev_batch(args):
     n = args.samples
     t0 = time.perf_counter()
     # sphere packings on the host, before the GPU is touched
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        gen = sorted(pool.map(_gen_rev, range(n), chunksize=4), key=lambda r: r[0])
+    if args.gen_workers > 1:
+        with mp.get_context("fork").Pool(args.gen_workers) as pool:
+            gen = sorted(pool.map(_gen_rev, range(n), chunksize=4), key=lambda r: r[0])
+    else:  # no forked workers (e.g. under a profiler, whose signal handling a forked child inherits)
+        gen = []
+        for i in range(n):
+            gen.append(_gen_rev(i))
+            if (i + 1) % 32 == 0:
+                log(f"  {i + 1} of {n} samples generated ({time.perf_counter() - t0:.0f} s)")
     doms = [g[1] for g in gen]
     from paper_1507_06565_amd import workloads as W
     layout = "brick" if args.layout == "brick" else "aa"  # a batch runs AA or bricks
@@ -359,6 +366,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=2000, help="rev-batch: steps per persistent launch")
     ap.add_argument("--max-steps", type=int, default=2_000_000, help="rev-batch: cap per sample")
     ap.add_argument("--out", default=None, help="rev-batch: write per-sample K and profiles (JSON)")
+    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="rev-batch: host processes generating the cubes (1: in this process)")
     ap.add_argument("--fixed-steps", type=int, default=0,
                     help="rev-batch: time this many steps with every cube active (after 20 warm-up steps) "
                          "instead of the run to steady state")
