@@ -233,13 +233,16 @@ lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t flags);
 lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* block, int32_t* flags);
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps_per_trial);
 
-/* Launch shape of a batched context's persistent kernel: workgroup size
- * (256, 512 or 1024) and workgroups that step one domain together (1..64).
- * The persistent launch holds as many workgroups as can be resident; teams of
- * workgroups_per_domain pop domains from a largest-first queue.  Results are
- * bit-identical for every shape.  lbm_autotune on a batched context (before
- * any step) times every shape on steps_per_trial steps of all domains, keeps
- * the fastest and restores the rest state. */
+/* Launch shape of a batched context.  AA layout (one persistent kernel):
+ * workgroup size (256, 512 or 1024) and workgroups that step one domain
+ * together (1..64); the persistent launch holds as many workgroups as can be
+ * resident, and teams of workgroups_per_domain pop domains from a
+ * largest-first queue.  Brick layout (all domains in one brick array, one
+ * brick-sweep launch per step): workgroup size 64..1024 (one brick per
+ * wavefront); workgroups_per_domain is validated (1..64) and otherwise
+ * unused.  Results are bit-identical for every shape.  lbm_autotune on a
+ * batched context (before any step) times the shapes on steps_per_trial
+ * steps of all domains, keeps the fastest and restores the rest state. */
 lbm_status lbm_batch_set_launch(lbm_ctx* ctx, int32_t block, int32_t workgroups_per_domain);
 lbm_status lbm_batch_get_launch(lbm_ctx* ctx, int32_t* block, int32_t* workgroups_per_domain);
 
