@@ -63,6 +63,26 @@ def test_batch_equals_single_domain_runs_bitwise(layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_mixed_step_parities_bitwise(layout):
+    """Domains that stopped at different step counts (check every 7 steps, so
+    some stop on odd counts) and are then stepped together: each domain's
+    state is in the grid of its own parity, and every field still equals a
+    single-domain run of the same number of steps bit for bit."""
+    say("test_batch_mixed_step_parities_bitwise", layout)
+    lbm = _lbm()
+    doms = batch_domains()
+    ctx = lbm.Context(lbm.Geometry(doms), params(layout))
+    steps = ctx.run_to_steady(rel_tol=1e-4, check_every=7, max_steps=700)
+    say("steps", steps)
+    assert len(set(int(v) % 2 for v in steps)) == 2  # both parities present
+    ctx.step(5)
+    for i, d in enumerate(doms):
+        single = lbm.Context(lbm.Geometry(d), params(layout))
+        single.step(int(steps[i]) + 5)
+        assert np.array_equal(single.fields()[1], ctx.fields(i)[1]), i
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_batch_launch_shapes_bitwise(layout):
     say("test_batch_launch_shapes_bitwise", layout)
     lbm = _lbm()
