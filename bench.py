@@ -81,13 +81,15 @@ def sampled_window_check(dom, params, ctx_factory, geo, nsteps=8, nwin=12, seed=
 
 def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0):
     """The FP64 oracle, as it is, on a slab of the workload straddling the
-    bed surface; one step calibrates the step count to about budget_s."""
+    bed surface; after one untimed step (threads and pages warm up), two
+    timed steps calibrate the step count to about budget_s."""
     import oracle
 
     sim = oracle.Sim(dom, params, window=((0, 0, z0), (dom.nx, dom.ny, nz_win)), geometry=geo_oracle)
-    t = time.perf_counter()
     sim.step(1)
-    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    sim.step(2)
+    t1 = (time.perf_counter() - t) / 2
     nsteps = int(max(1, min(400, budget_s / max(t1, 1e-3))))
     t = time.perf_counter()
     sim.step(nsteps)
