@@ -139,6 +139,15 @@ def test_brick_layout_plan():
         gb = lbm.Geometry(W.Domain(*shape))
         assert _status(lambda: lbm.required_bytes(gb, W.Params(layout="brick"))) == E_INVAL
         assert lbm.required_bytes(gb, W.Params(layout="twogrid")) > 0
+    # batches: every domain's bricks in one array (two grids), each domain's range
+    # padded to a multiple of 8 bricks; a domain not divisible by 4 is rejected
+    per = lambda dd: W.Domain(dd, dd, dd, periodic=(1, 1, 1), wall_lo=(0, 0, 0), wall_hi=(0, 0, 0))
+    gbatch = lbm.Geometry([per(16), per(12), per(20)])
+    nb = sum(-(-(e // 4) ** 3 // 8) * 8 for e in (16, 12, 20))  # all fluid: every brick stored, padded
+    assert lbm.required_bytes(gbatch, W.Params(layout="brick", force=(1e-5, 0, 0))) >= 2 * 19 * 4 * 64 * nb
+    gbad = lbm.Geometry([per(16), per(18)])
+    assert _status(lambda: lbm.required_bytes(gbad, W.Params(layout="brick", force=(1e-5, 0, 0)))) == E_INVAL
+    assert lbm.required_bytes(gbad, W.Params(layout="aa", force=(1e-5, 0, 0))) > 0
 
 
 def test_closure_and_gray_argument_validation():
