@@ -243,3 +243,29 @@ def test_rev_workload_representative_permeability(layout):
         k = ctx.permeability(i, 0)
         say("sample", g["index"], "edge", g["edge"], "porosity", round(g["porosity"], 4), "K", k, "oracle", g["K"])
         assert abs(k / g["K"] - 1) <= 1e-4, (g["index"], k, g["K"])
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_batch_walled_bouzidi_and_moving_lid_bitwise(layout):
+    """Batches of walled domains: spheres between wall layers with Bouzidi
+    links, and Couette cells under a moving lid (the lid's partial values are
+    seeded per domain); every domain equals its single-domain run bit for bit."""
+    say("test_batch_walled_bouzidi_and_moving_lid_bitwise", layout)
+    lbm = _lbm()
+    rng = np.random.default_rng(77)
+    walled = []
+    for i, (nx, ny, nz) in enumerate([(16, 12, 20), (24, 8, 16), (12, 16, 24)]):
+        S = W.quantise(np.column_stack([rng.uniform(0, nx, 4), rng.uniform(0, ny, 4), rng.uniform(2, nz - 2, 4),
+                                        rng.uniform(2.0, 4.5, 4)]))
+        walled.append(W.Domain(nx, ny, nz, spheres=S, bc="bouzidi"))
+    lids = [W.Domain(8, 4, 20, wall_hi_velocity=(2e-3, 0.0, 0.0), bc="cli"),
+            W.Domain(4, 8, 16, wall_hi_velocity=(2e-3, 0.0, 0.0), bc="cli")]
+    pw = W.Params(**{**params(layout).__dict__, "force": (1e-5, 0.0, 0.0)})
+    pl = W.Params(**{**params(layout).__dict__, "force": (0.0, 0.0, 0.0)})
+    for doms, p in ((walled, pw), (lids, pl)):
+        ctx = lbm.Context(lbm.Geometry(doms), p)
+        ctx.step(33)
+        for i, d in enumerate(doms):
+            single = lbm.Context(lbm.Geometry(d), p)
+            single.step(33)
+            assert np.array_equal(single.fields()[1], ctx.fields(i)[1]), (i, d.bc)
