@@ -341,3 +341,28 @@ def test_maximum_domain_size_channel():
     assert np.array_equal(por, rp)
     assert e <= REL_L2
     assert abs(m) <= 1e-6 * (1 << 30)
+
+
+def test_c2_full_size_brick_equals_aa_bitwise():
+    """The large bed (512x256x1024) after 20 steps in the brick layout and in
+    the AA layout, each with its autotuned launch: the FP64 plane profiles
+    along all three axes and the totals, computed from the two states, agree
+    bit for bit (the layouts share the cell arithmetic)."""
+    say("test_c2_full_size_brick_equals_aa_bitwise")
+    lbm = _lbm()
+    d, p, _ = W.large_c2()
+    g = lbm.Geometry(d)
+    out = {}
+    for layout in ("brick", "aa"):
+        ctx = lbm.Context(g, W.Params(**{**p.__dict__, "layout": layout}))
+        ctx.autotune(4)
+        ctx.step(20)
+        prof = [ctx.average_profile(0, axis, comp) for axis in (0, 1, 2) for comp in (0, 1, 2)]
+        out[layout] = (prof, ctx.totals())
+        del ctx
+    for pa, pb in zip(out["brick"][0], out["aa"][0]):
+        for x, y in zip(pa, pb):
+            assert np.array_equal(x, y)
+    assert out["brick"][1][0] == out["aa"][1][0]
+    assert np.array_equal(out["brick"][1][1], out["aa"][1][1])
+    assert out["brick"][1][1][0] > 0
