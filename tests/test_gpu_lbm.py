@@ -287,18 +287,20 @@ def test_c2_full_size_sampled_windows(layout):
     assert e <= REL_L2
 
 
-def test_c1_20000_steps_against_stored_oracle():
+@pytest.mark.parametrize("layout", ["twogrid", "brick"])
+def test_c1_20000_steps_against_stored_oracle(layout):
     """The coupled bed (Bouzidi) over its full 20000 steps in FP32 against the
     FP64 oracle's state stored by tests/golden/make_c1_drift.py: 4096 sampled
     fluid cells and the plane-averaged superficial profile."""
     import json
     import os
-    say("test_c1_20000_steps_against_stored_oracle")
+    say("test_c1_20000_steps_against_stored_oracle", layout)
     lbm = _lbm()
     path = os.path.join(os.path.dirname(__file__), "golden", "c1_20000.json")
     with open(path) as f:
         gold = json.load(f)
     d, p, eps = W.coupled_c1()
+    p = W.Params(**{**p.__dict__, "layout": layout})
     assert abs(eps - gold["bed_porosity"]) == 0
     ctx = lbm.Context(lbm.Geometry(d), p)
     ctx.step(gold["steps"])
