@@ -368,3 +368,17 @@ def test_c2_full_size_brick_equals_aa_bitwise():
     assert out["brick"][1][0] == out["aa"][1][0]
     assert np.array_equal(out["brick"][1][1], out["aa"][1][1])
     assert out["brick"][1][1][0] > 0
+
+
+@pytest.mark.parametrize("layout", ["twogrid", "aa"])
+def test_channel_xy_invariance_bitwise(layout):
+    """The C0 channel is invariant in x and y: a 1x1x32 column (every
+    neighbour in x and y is the cell itself) gives the same u_x(z) as the
+    32x32x32 channel bit for bit, after 500 steps."""
+    say("test_channel_xy_invariance_bitwise", layout)
+    p = W.Params(collision="bgk", tau_plus=0.8, force=(1e-6, 0, 0), layout=layout)
+    _, _, u1 = gpu_run(W.Domain(1, 1, 32, bc="sbb"), p, 500, layout)
+    _, _, u32 = gpu_run(W.Domain(32, 32, 32, bc="sbb"), p, 500, layout)
+    col = u1[0, :, 0, 0]
+    assert np.all(u32[0] == col[:, None, None])
+    assert col[16] > 0
