@@ -403,3 +403,29 @@ def test_trt_poiseuille_steady_closed_form(layout):
     err = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
     say("relative L2 against the closed form", err)
     assert err <= REL_L2
+
+
+@pytest.mark.parametrize("layout", ["brick", "aa"])
+def test_sphere_array_permeability_against_dilute_expansion(layout):
+    """Curved CLI walls and Darcy's law on the GPU alone: the permeability of a
+    simple-cubic sphere array (one sphere of radius L/4 in a periodic cube of
+    edge L, TRT Lambda 3/16) run to steady state against the Hasimoto /
+    Sangani-Acrivos dilute expansion K = L^3 / (6 pi a K*); within 2 % at
+    every resolution, and closer at the finest than at the coarsest
+    (measured 0.61 %, 0.009 %, 0.063 % for L = 16, 32, 64)."""
+    import math
+    say("test_sphere_array_permeability_against_dilute_expansion", layout)
+    lbm = _lbm()
+    errs = []
+    for L, a in [(16, 4), (32, 8), (64, 16)]:
+        c = 4 * math.pi * a ** 3 / (3 * L ** 3)
+        inv = 1 - 1.7601 * c ** (1 / 3) + c - 1.5593 * c ** 2 + 3.9799 * c ** (8 / 3) - 3.0734 * c ** (10 / 3)
+        Kref = L ** 3 / (6 * math.pi * a / inv)
+        p = W.Params(collision="trt", tau_plus=1.0, magic_lambda=3 / 16, force=(1e-6, 0, 0), layout=layout)
+        ctx = lbm.Context(lbm.Geometry(W.cubic_array(L, a)), p)
+        steps = ctx.run_to_steady(1e-7, 100, 400000)
+        K = ctx.permeability()
+        errs.append(abs(K / Kref - 1))
+        say("L", L, "a", a, "steps", int(steps[0]), "K", K, "expansion", Kref, "error", errs[-1])
+        assert errs[-1] < 0.02, (L, a, K, Kref)
+    assert errs[2] < errs[0]
