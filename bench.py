@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+CHECK_STEPS = 20  # steps of the sampled-window FP32-vs-FP64 check (short horizon, from rest)
 
 
 def log(*a):
@@ -43,10 +44,12 @@ def algorithmic_bytes(n_fluid, n_cells, n_links):
     return 152 * n_fluid + 4 * n_cells + 12 * n_links
 
 
-def sampled_window_check(dom, params, ctx_factory, geo, nsteps=8, nwin=12, seed=0):
-    """FP32 GPU vs FP64 oracle on sampled cells of the full-size domain: each
-    sampled cell's neighbourhood is run on the oracle in a window whose edge is
-    more than nsteps cells away (one cell of light cone per step)."""
+def sampled_window_check(dom, params, ctx_factory, geo, nsteps=20, nwin=16, seed=0):
+    """FP32 GPU vs FP64 oracle on sampled cells of the full-size domain: the
+    oracle runs a window of edge 2 (nsteps + 2) + 6 around each sample and the
+    6^3 cells at its centre, more than nsteps + 1 cells from its edge (one
+    cell of light cone per step), are compared with the GPU's full-domain
+    run."""
     import numpy as np
 
     import oracle
@@ -56,7 +59,7 @@ def sampled_window_check(dom, params, ctx_factory, geo, nsteps=8, nwin=12, seed=
     _, u = ctx.fields()
     rng = np.random.default_rng(seed)
     h = nsteps + 2
-    w = 2 * h + 4
+    w = 2 * h + 6
     num = den = 0.0
     for _ in range(nwin):
         cz = int(rng.integers(h + 1, dom.nz - h - 5))
@@ -101,6 +104,17 @@ def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0):
                       f"{nsteps} steps, FP64 two-grid, {dt:.1f} s"}
 
 
+def gpu_runtime_loaded():
+    """True if the HIP or HSA runtime is mapped into this process (then the
+    GPU may already be initialised, and the process must not fork)."""
+    try:
+        with open("/proc/self/maps") as f:
+            maps = f.read()
+    except OSError:
+        return True
+    return "libamdhip64" in maps or "libhsa-runtime64" in maps
+
+
 def _gen_rev(i):
     from paper_1507_06565_amd import workloads as W
     d, p, target, eps = W.rev_sample_c3(i)
@@ -120,11 +134,19 @@ def rev_batch(args):
 
     n = args.samples
     t0 = time.perf_counter()
-    # sphere packings on the host, before the GPU is touched
-    if args.gen_workers > 1:
-        with mp.get_context("fork").Pool(args.gen_workers) as pool:
+    # sphere packings on the host.  Worker processes are forked only while no
+    # GPU runtime is mapped into this process: a profiler's preload library
+    # initialises the GPU before main(), and a child forked from such a
+    # process inherits GPU state and the profiler's signal handlers (it has
+    # crashed at exit, and hung, under rocprofv3).
+    workers = args.gen_workers
+    if workers > 1 and gpu_runtime_loaded():
+        log("a GPU runtime is already loaded in this process (profiler preload?): generating in-process")
+        workers = 1
+    if workers > 1:
+        with mp.get_context("fork").Pool(workers) as pool:
             gen = sorted(pool.map(_gen_rev, range(n), chunksize=4), key=lambda r: r[0])
-    else:  # no forked workers (e.g. under a profiler, whose signal handling a forked child inherits)
+    else:
         gen = []
         for i in range(n):
             gen.append(_gen_rev(i))
@@ -413,9 +435,11 @@ def main():
         log(f"oracle geometry ({time.perf_counter() - t0:.1f} s)")
     if not args.no_check:
         t0 = time.perf_counter()
-        check = sampled_window_check(dom, params, lambda: lbm.Context(geo, params), geo_oracle, nsteps=8, nwin=12)
+        check = sampled_window_check(dom, params, lambda: lbm.Context(geo, params), geo_oracle,
+                                     nsteps=CHECK_STEPS, nwin=16)
         torch.cuda.empty_cache()
-        log(f"sampled-window FP32 vs FP64 rel L2 after 8 steps: {check:.3e} ({time.perf_counter() - t0:.1f} s)")
+        log(f"sampled-window FP32 vs FP64 rel L2 after {CHECK_STEPS} steps: {check:.3e} "
+            f"({time.perf_counter() - t0:.1f} s)")
 
     if args.copy_probe:
         a = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
@@ -486,6 +510,7 @@ def main():
         "mflups": round(mflups, 1),
         "effective_gbs": round(achieved, 1),
         "fp32_rel_l2_vs_fp64_oracle": check,
+        "fp32_check": f"sampled windows, {CHECK_STEPS} steps from rest (short horizon)" if check is not None else None,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg,

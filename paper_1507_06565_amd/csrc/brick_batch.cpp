@@ -127,6 +127,7 @@ lbm_status plan(const std::vector<DomainGeo>& G, const lbm_params& p, BrickBatch
     b.NS = nb * 64;
     if (b.NS >= ((int64_t)1 << 30))
         return set_error(LBM_E_INVAL, "a brick-layout batch must store fewer than 2^30 cells");
+    if (nl > max_links()) return set_error(LBM_E_INVAL, "too many boundary links in one batch (limit 2^30 - 19)");
     b.nl = nl;
     b.nbmap = nbmap;
     b.nseed = nseed;

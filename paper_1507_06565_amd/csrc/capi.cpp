@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -130,6 +131,16 @@ std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 }  // namespace
 
 lbm_status lbm::set_error(lbm_status s, const std::string& msg) { return fail(s, msg); }
+
+int64_t lbm::max_links() {
+    const int64_t hard = ((int64_t)1 << 30) - Q;
+    const char* e = std::getenv("MI355LBM_MAX_LINKS");
+    if (e && *e) {
+        const long long v = std::strtoll(e, nullptr, 10);
+        if (v >= 0 && v < hard) return (int64_t)v;
+    }
+    return hard;
+}
 
 struct lbm_ctx {
     int ndom = 1;
@@ -349,6 +360,8 @@ lbm_status lbm_required_bytes(const lbm_geometry* g, const lbm_params* p, int64_
             if (!brick_dims_ok(g->doms[0].desc)) return fail(LBM_E_INVAL, "brick layout needs nx, ny, nz divisible by 4");
             build_brick_map(g->doms[0], bm, false);
         }
+        if ((int64_t)g->doms[0].lcell.size() > max_links())
+            return fail(LBM_E_INVAL, "too many boundary links in one domain (limit 2^30 - 19)");
         *bytes = plan_single(g->doms[0], *p, bm).total;
         return LBM_OK;
     }
@@ -384,6 +397,10 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
         return LBM_OK;
     }
     const DomainGeo& G = g->doms[0];
+    if ((int64_t)G.lcell.size() > max_links()) {
+        delete c;
+        return fail(LBM_E_INVAL, "too many boundary links in one domain (limit 2^30 - 19)");
+    }
     BrickMap bm;
     if (p->layout == LBM_LAYOUT_BRICK) {
         if (!brick_dims_ok(G.desc)) {

@@ -42,6 +42,13 @@ constexpr uint32_t CELL_SOLID_WORD = 0xFFFFFFFFu;
 constexpr int SEG_SHIFT = 9;
 constexpr uint32_t LINK_MASK_BITS = 0x3FFFFu;
 
+// Link coefficients and partial values are addressed by 32-bit byte offsets
+// (4 x link index, index < nl + Q with the padding) and segment bases are
+// int32, so one domain, or one brick-layout batch, may hold at most
+// max_links() = 2^30 - Q links.  The environment variable
+// MI355LBM_MAX_LINKS can only lower this limit (for tests of the check).
+int64_t max_links();
+
 enum Layout : int { L_TWOGRID = 0, L_AA = 1, L_BRICK = 2 };
 enum Parity : int { P_EVEN = 0, P_ODD = 1 };
 

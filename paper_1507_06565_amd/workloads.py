@@ -245,13 +245,40 @@ def voxel_solid_count(S, shape, periodic, z_range=None) -> int:
     return int(solid.sum())
 
 
-def porous_bed(seed, nx, ny, nz, bed_top, r_range, porosity, tol=0.01, max_tries=6):
+class PackingError(RuntimeError):
+    """No attempt of the generator met the porosity and radius tolerances."""
+
+
+# Jam shrinking and overlap repair may take radii somewhat below the lower end
+# of the drawn range; an attempt is accepted only if no radius fell below this
+# fraction of it.
+R_SHRINK_MIN = 0.95
+# further seeds tried (seed + RESEED * k) when the volume-steered attempts miss
+RESEED = 1_000_000
+RESEED_TRIES = 24
+
+
+def packing_ok(S, r_range, eps, porosity, tol):
+    """Acceptance of a packing: voxel porosity within tol of the target and
+    every radius in [R_SHRINK_MIN * r_lo, r_hi]."""
+    if abs(eps - porosity) > tol:
+        return False
+    if len(S) == 0:
+        return True
+    return bool(S[:, 3].min() >= R_SHRINK_MIN * r_range[0] and S[:, 3].max() <= r_range[1])
+
+
+def porous_bed(seed, nx, ny, nz, bed_top, r_range, porosity, tol=0.01, max_tries=6, reseeds=RESEED_TRIES):
     """Spheres filling the bed layers [1, bed_top) of a channel with wall
     layers at z = 0 and z = nz-1, periodic in x and y.
 
     Centre heights obey z_c + r <= bed_top and z_c - r >= 0.5 - 2*rbar, so
     spheres may be cut by the bottom wall (no wall-induced porosity layer).
-    The voxel porosity of layers [1, bed_top) is steered to the target.
+    The voxel porosity of layers [1, bed_top) is steered to the target by
+    rescaling the sphere volume over max_tries attempts (the first three with
+    the given seed); if none is accepted (packing_ok), further seeds
+    seed + RESEED * k (k = 1 .. reseeds) are tried; PackingError if every
+    attempt misses.
     """
     rbar = 0.5 * (r_range[0] + r_range[1])
     bed_cells = nx * ny * (bed_top - 1)
@@ -261,34 +288,49 @@ def porous_bed(seed, nx, ny, nz, bed_top, r_range, porosity, tol=0.01, max_tries
         return z_lo_plane + R, bed_top - R
 
     target_solid = (1.0 - porosity) * bed_cells
-    vol = target_solid
-    S = None
-    for attempt in range(max_tries):
-        S = pack_spheres(seed + 1000003 * attempt if attempt >= 3 else seed,
-                         (nx, ny, bed_top), (1, 1, 0), r_range, vol,
-                         zc_bounds=zc_bounds)
+
+    def attempt(sd, vol):
+        S = pack_spheres(sd, (nx, ny, bed_top), (1, 1, 0), r_range, vol, zc_bounds=zc_bounds)
         solid = voxel_solid_count(S, (nx, ny, nz), (1, 1, 0), (1, bed_top))
-        eps = 1.0 - solid / bed_cells
-        if abs(eps - porosity) <= tol:
+        return S, 1.0 - solid / bed_cells, solid
+
+    vol = target_solid
+    for k in range(max_tries):
+        S, eps, solid = attempt(seed + 1000003 * k if k >= 3 else seed, vol)
+        if packing_ok(S, r_range, eps, porosity, tol):
             return S, eps
         vol *= target_solid / max(solid, 1.0)
-    return S, eps
+    for k in range(1, reseeds + 1):
+        vol = target_solid
+        for _ in range(3):
+            S, eps, solid = attempt(seed + RESEED * k, vol)
+            if packing_ok(S, r_range, eps, porosity, tol):
+                return S, eps
+            vol *= target_solid / max(solid, 1.0)
+    raise PackingError(f"bed {nx}x{ny}x{nz} (seed {seed}): no packing within {tol} of porosity {porosity}")
 
 
-def rev_cube(seed, edge, r_range, porosity, tol=0.02, max_tries=6):
-    """Periodic cube of edge cells filled to a target voxel porosity."""
+def rev_cube(seed, edge, r_range, porosity, tol=0.02, max_tries=6, reseeds=RESEED_TRIES):
+    """Periodic cube of edge cells filled to a target voxel porosity: the
+    sphere volume is rescaled over max_tries attempts with the given seed,
+    then further seeds seed + RESEED * k (k = 1 .. reseeds) are tried;
+    PackingError if no attempt meets packing_ok."""
     cells = edge ** 3
     target_solid = (1.0 - porosity) * cells
-    vol = target_solid
-    S, eps = None, 1.0
-    for attempt in range(max_tries):
-        S = pack_spheres(seed, (edge, edge, edge), (1, 1, 1), r_range, vol)
+
+    def attempt(sd, vol):
+        S = pack_spheres(sd, (edge, edge, edge), (1, 1, 1), r_range, vol)
         solid = voxel_solid_count(S, (edge,) * 3, (1, 1, 1))
-        eps = 1.0 - solid / cells
-        if abs(eps - porosity) <= tol:
-            break
-        vol *= target_solid / max(solid, 1.0)
-    return S, eps
+        return S, 1.0 - solid / cells, solid
+
+    for k in range(reseeds + 1):
+        vol = target_solid
+        for _ in range(max_tries if k == 0 else 3):
+            S, eps, solid = attempt(seed + RESEED * k, vol)
+            if packing_ok(S, r_range, eps, porosity, tol):
+                return S, eps
+            vol *= target_solid / max(solid, 1.0)
+    raise PackingError(f"REV cube {edge}^3 (seed {seed}): no packing within {tol} of porosity {porosity}")
 
 
 # ----------------------------------------------------------------------------

@@ -124,6 +124,26 @@ def test_aa_equals_twogrid_bitwise():
         assert np.array_equal(u1, u2) and np.array_equal(r1, r2), n
 
 
+@pytest.mark.parametrize("layout", ["twogrid", "aa", "brick"])
+def test_cli_and_bouzidi_equal_sbb_when_every_q_is_half(layout):
+    """Planar walls only (wall layers on y and z, periodic x), so every link
+    has q = 1/2, where CLI's kappa = (1 - 2q)/(1 + 2q) vanishes and Bouzidi's
+    rule becomes simple bounce-back (eq. (CLI), eq. (noslip)): after 300 steps
+    of a flow driven along all three axes the three schemes give bit-identical
+    fields."""
+    say("test_cli_and_bouzidi_equal_sbb_when_every_q_is_half", layout)
+    p = W.Params(collision="trt", tau_plus=0.7, magic_lambda=3 / 16, force=(2e-5, 1e-5, 3e-6))
+    out = {}
+    for bc in ("sbb", "cli", "bouzidi"):
+        d = W.Domain(16, 12, 20, periodic=(1, 0, 0), wall_lo=(0, 1, 1), wall_hi=(0, 1, 1), bc=bc)
+        _, r, u = gpu_run(d, p, 300, layout)
+        out[bc] = (r, u)
+    for bc in ("cli", "bouzidi"):
+        assert np.array_equal(out[bc][0], out["sbb"][0]), bc
+        assert np.array_equal(out[bc][1], out["sbb"][1]), bc
+    assert np.abs(out["sbb"][1][0]).max() > 1e-5
+
+
 def test_launch_shapes_bitwise():
     say("test_launch_shapes_bitwise")
     # nx = 128: workgroups of 64 and 128 cells cover whole rows (row mapping),
@@ -239,9 +259,10 @@ def test_c1_full_size_parity():
 def test_c2_full_size_sampled_windows(layout):
     """C2 at full size (512x256x1024, CLI, TRT 3/16, tau 0.7) in the launch
     configuration the benchmark uses (brick layout, autotuned; and the AA
-    layout): 8 steps from rest, then sampled cells against oracle windows
-    whose edge is more than 8 cells away (the light cone of 8 steps); also the
-    bed porosity and plane porosity profile."""
+    layout): 20 steps from rest, then sampled cells against oracle windows
+    of edge 2 (20 + 2) + 6 = 50 whose 6^3 central cells are more than 21
+    cells from the window edge (the light cone of 20 steps); also the bed
+    porosity and plane porosity profile."""
     say("test_c2_full_size_sampled_windows", layout)
     lbm = _lbm()
     d, p, eps = W.large_c2()
@@ -250,7 +271,7 @@ def test_c2_full_size_sampled_windows(layout):
     g = lbm.Geometry(d)
     ctx = lbm.Context(g, p)
     ctx.autotune(4)
-    nsteps = 8
+    nsteps = 20
     ctx.step(nsteps)
     _, u = ctx.fields()
     _, _, por = ctx.average_profile(0, 2, 0)

@@ -40,9 +40,12 @@ def setup(B=192, seed=0):
     return net, pr, Xr, xb, rng
 
 
-def test_forward_and_backward_parity():
-    say("test_forward_and_backward_parity")
-    net, pr, Xr, xb, rng = setup()
+@pytest.mark.parametrize("B", [192, 8192])
+def test_forward_and_backward_parity(B):
+    """B = 8192: 128 workgroups of partial gradients summed by the fixed-order
+    reduction kernel, the batch size of a training step."""
+    say("test_forward_and_backward_parity", B)
+    net, pr, Xr, xb, rng = setup(B=B, seed=B)
     y = net.forward(xb, train=True).cpu().numpy().astype(np.float64)
     Yr, cache = R.forward(pr, Xr)
     e = rel(y, Yr)

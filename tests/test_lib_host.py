@@ -166,3 +166,30 @@ def test_closure_and_gray_argument_validation():
     # null pointers and sizes out of range are rejected up front
     assert lib.mlp_profile_loss(None, None, None, 1, 64, 0.1, 1e-6, 1.0, None, None, None) == E_INVAL
     assert lib.mlp_closure(None, None, 10, 0.1, None, None, None) == E_INVAL
+
+
+def test_link_count_limit(monkeypatch):
+    """Link records and partial values are addressed by 32-bit byte offsets:
+    a domain or a brick-layout batch with more links than the limit is
+    refused with LBM_E_INVAL (the limit is lowered through the environment so
+    that a small geometry can cross it)."""
+    from paper_1507_06565_amd import lbm
+    d, _, _ = W.coupled_c1()
+    g = lbm.Geometry(d)
+    nl = g.info()[2]
+    for layout in ("twogrid", "aa", "brick"):
+        p = W.Params(collision="trt", tau_plus=0.7, magic_lambda=3 / 16, layout=layout)
+        monkeypatch.setenv("MI355LBM_MAX_LINKS", str(nl))
+        assert lbm.required_bytes(g, p) > 0
+        monkeypatch.setenv("MI355LBM_MAX_LINKS", str(nl - 1))
+        with pytest.raises(lbm.LbmError, match="too many boundary links"):
+            lbm.required_bytes(g, p)
+    cubes = [W.rev_sample_c3(i)[0] for i in (0, 1)]
+    gb = lbm.Geometry(cubes)
+    nlb = sum(gb.info(i)[2] for i in range(2))
+    p = W.Params(collision="trt", tau_plus=1.0, magic_lambda=3 / 16, layout="brick")
+    monkeypatch.setenv("MI355LBM_MAX_LINKS", str(nlb))
+    assert lbm.required_bytes(gb, p) > 0
+    monkeypatch.setenv("MI355LBM_MAX_LINKS", str(nlb - 1))
+    with pytest.raises(lbm.LbmError, match="too many boundary links"):
+        lbm.required_bytes(gb, p)
