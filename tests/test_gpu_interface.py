@@ -1,0 +1,60 @@
+"""Two-domain interface evaluation on a profile the GPU produced: a coupled
+bed (64 x 32 x 128, bed layers [1, 64), radii U[3,5], porosity 0.6) run from
+rest to steady state by the library, then the fits, slip and jump
+coefficients, analytic two-domain profiles and the parameter study of
+Sec. 3.2 on the host."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.mark.timeout(300)
+def test_interface_study_on_gpu_steady_profile():
+    from paper_1507_06565_amd import interface as I
+    from paper_1507_06565_amd import workloads as W
+
+    S, eps_bed = W.porous_bed(41, 64, 32, 128, 64, (3.0, 5.0), 0.6)
+    dom = W.Domain(64, 32, 128, spheres=S, bc="cli", name="bed-64x32x128")
+    p = W.Params(collision="trt", tau_plus=1.0, magic_lambda=3 / 16, force=(1e-6, 0, 0), layout="aa")
+    nu, G = 0.5 / 3.0, 1e-6
+    u, por, steps, sec = I.steady_profile(dom, p, 64)
+    say(f"steady after {steps} steps, {sec:.2f} s; bed porosity {eps_bed:.4f}")
+    assert steps < 2_000_000
+    # the profile: no-slip walls, positive in every fluid layer, the free
+    # channel's maximum well above the bed's Darcy velocity
+    assert u[0] == 0.0 and u[-1] == 0.0
+    assert np.all(u[1:-1] > 0)
+    assert np.all(por[65:127] == 1.0) and abs(np.mean(por[16:48]) - eps_bed) < 0.05
+    res = I.study(u, por, 64, nu, G)
+    lim, app = res["porosity_limit"], res["apparent"]
+    say({k: (round(v["zi"], 1), round(v["alpha"], 3), round(v["beta"], 3), round(v["err_BJ"], 4),
+             round(v["err_Br"], 4), round(v["err_OTW"], 4)) for k, v in (("limit", lim), ("apparent", app))})
+    assert 55 < lim["zi"] < 66 and app["zi"] <= lim["zi"]
+    for r in (lim, app):
+        # the fitted coefficients satisfy their definitions with the fitted
+        # slopes (eqs. (BJ), (OTW))
+        sk = math.sqrt(r["K"])
+        assert abs(r["alpha"] * (r["Us"] - r["Um"]) - sk * r["dU_plus"]) <= 1e-9 * abs(sk * r["dU_plus"])
+        assert np.isfinite(r["beta"])
+        assert r["rms_free"] < 0.01
+        # the BJ analytic profile with the fitted alpha follows the pore-scale
+        # one to a few per cent (Sec. 3.2: close, but not exact)
+        assert r["err_BJ"] < 0.1
+        sens = r["sensitivity"]
+        # the misfit search can only improve on the fitted parameters
+        assert sens["best"]["BJ"]["err"] <= r["err_BJ"] + 1e-9
+        assert sens["best"]["OTW"]["err"] <= r["err_OTW"] + 1e-9 or r["beta"] >= sens["otw_pole_beta"]
+        mx = [e["u_max"] for e in sens["Br"]]
+        assert all(a > b for a, b in zip(mx, mx[1:]))
+        bj = [e["u_max"] for e in sens["BJ"]]
+        assert all(a > b for a, b in zip(bj, bj[1:]))
+    # K of the bed interior: positive and of the order of the grain size squared
+    assert 0.01 < lim["K"] < 10.0

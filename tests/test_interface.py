@@ -74,3 +74,50 @@ def test_two_domain_brinkman_solution_satisfies_its_equations():
 def test_brinkman_far_field_is_darcy():
     U = I.stokes_brinkman(150.5, 254.5, 0.5, G, NU, 2.0, 0.5, 2.0, 0.0)
     assert abs(U(60.0) / (2.0 * G / NU) - 1) < 1e-9
+
+
+def test_saffman_profile_is_beavers_joseph_without_seepage():
+    """eq. (BJS): sqrt(K)/alpha U'(zi+) = U_s, i.e. BJ with U_m = 0."""
+    zi, top, K, alpha = 120.5, 254.5, 1.7, 0.4
+    f = I.stokes_bjs(zi, top, G, NU, K, alpha)
+    g = I.stokes_bj(zi, top, G, NU, K, 0.0, alpha)
+    s = np.linspace(0.0, top - zi, 101)
+    assert np.array_equal(f(s), g(s))
+    h = 1e-3  # the profile is quadratic: the centred difference of f at h is exact up to rounding
+    slope = (-3 * f(0.0) + 4 * f(h) - f(2 * h)) / (2 * h)
+    assert abs(math.sqrt(K) / alpha * slope - f(0.0)) < 1e-9 * f(0.0)
+    assert abs(f(top - zi)) < 1e-15
+
+
+def test_sensitivity_reproduces_the_parameter_study():
+    """Sec. 3.2's observations on the analytic two-domain profiles: raising the
+    viscosity ratio J of Br lowers the maximum velocity and makes the shear
+    rate jump by 1/J across the interface; negative OTW jump coefficients
+    change the profile little, positive ones strongly; BJ and BJS are nearly
+    the same at low Re; the maximum falls as alpha grows and a small alpha
+    gives a much larger maximum.  Also: the profile-misfit search returns the
+    alpha a BJ profile was built with."""
+    u, eps, Um, Us = synthetic(0.5, 0.0)
+    r = I.sensitivity(u, eps, 120.5, 128, NU, G)
+    br = r["Br"]
+    assert [e["J"] for e in br] == sorted(e["J"] for e in br)
+    mx = [e["u_max"] for e in br]
+    assert all(a > b for a, b in zip(mx, mx[1:])), mx
+    for e in br:
+        assert abs(e["slope_ratio"] * e["J"] - 1) < 1e-4, e
+    otw = {e["beta"]: e["u_max"] for e in r["OTW"]}
+    neg = abs(otw[-4.0] - otw[0.0])
+    pos = abs(otw[0.5] - otw[0.0])
+    assert pos > 0.8 * neg and pos / 0.5 > 4 * neg / 4.0, (neg, pos)
+    # near the pole the profile grows without bound
+    bs = r["otw_pole_beta"]
+    assert 0 < bs < 5
+    U = I.stokes_brinkman(120.5, 254.5, 0.5, G, NU, r["K"], r["eps_bed"], 1 / r["eps_bed"], bs * (1 - 1e-6))
+    assert abs(U(200.0)) > 1e3 * r["umax"]
+    bj = [e["u_max"] for e in r["BJ"]]
+    bjs = [e["u_max"] for e in r["BJS"]]
+    assert all(a > b for a, b in zip(bj, bj[1:])), bj
+    assert bj[0] > 1.5 * bj[-1]
+    assert max(abs(a / b - 1) for a, b in zip(bj, bjs)) < 1e-3
+    assert abs(r["best"]["BJ"]["alpha"] / 0.5 - 1) < 1e-6
+    assert r["best"]["Br"]["err"] <= min(e["err"] for e in br) + 1e-12
