@@ -154,7 +154,8 @@ def rev_batch(args):
                 log(f"  {i + 1} of {n} samples generated ({time.perf_counter() - t0:.0f} s)")
     doms = [g[1] for g in gen]
     from paper_1507_06565_amd import workloads as W
-    layout = "brick" if args.layout == "brick" else "aa"  # a batch runs AA or bricks
+    # a batch runs AA (persistent launch) or bricks (brick-list launches)
+    layout = {"twogrid": "aa"}.get(args.layout, args.layout)
     params = W.Params(**{**gen[0][2].__dict__, "layout": layout})
     log(f"{n} REV samples generated ({time.perf_counter() - t0:.1f} s); edges "
         f"{dict(zip(*np.unique([d.nx for d in doms], return_counts=True)))}")
@@ -170,6 +171,13 @@ def rev_batch(args):
     log(f"geometry: {cells.sum()} cells, {info[:, 0].sum()} fluid, {info[:, 1].sum()} links "
         f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.set_device(0)
+    if layout == "auto":
+        t1 = time.perf_counter()
+        layout, ms_tuned = lbm.autotune_layout(geo, params, steps_per_trial=10)
+        params = W.Params(**{**params.__dict__, "layout": layout})
+        torch.cuda.empty_cache()
+        log(f"layout autotuner: {layout} ({ms_tuned:.3f} ms per step with every cube active; "
+            f"{time.perf_counter() - t1:.1f} s)")
     ctx = lbm.Context(geo, params)
     if args.launch:
         block, W0 = (int(v) for v in args.launch.split(","))
@@ -376,8 +384,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
-    ap.add_argument("--layout", choices=("aa", "twogrid", "brick"), default="brick",
-                    help="bed: population layout of the sweep")
+    ap.add_argument("--layout", choices=("auto", "aa", "twogrid", "brick"), default="auto",
+                    help="bed: population layout of the sweep (auto: the library's layout autotuner)")
     ap.add_argument("--launch", default=None, metavar="BLOCK,FLAGS",
                     help="fixed launch shape instead of the autotuner: bed BLOCK,FLAGS (e.g. 1024,2); "
                          "rev-batch BLOCK,WORKGROUPS_PER_SAMPLE")
@@ -425,6 +433,14 @@ def main():
     n_cells = dom.nx * dom.ny * dom.nz
 
     torch.cuda.set_device(0)
+    layout_tuned = None
+    if params.layout == "auto":
+        t0 = time.perf_counter()
+        name, ms_tuned = lbm.autotune_layout(geo, params, steps_per_trial=10)
+        params = W.Params(**{**params.__dict__, "layout": name})
+        layout_tuned = {"chosen": name, "trial_ms_per_step": round(ms_tuned, 4)}
+        torch.cuda.empty_cache()
+        log(f"layout autotuner: {name} ({ms_tuned:.3f} ms per step in its trial; {time.perf_counter() - t0:.1f} s)")
     check = None
     geo_oracle = None
     if not args.no_check or not args.no_cpu_baseline:
@@ -477,7 +493,7 @@ def main():
     mlups = n_cells / (ms_per_step * 1e-3) / 1e6
     mflups = n_fluid / (ms_per_step * 1e-3) / 1e6
     traffic = None
-    tf = os.path.join(ROOT, "profiles", f"sweep_{args.layout}_512x256x1024_traffic.json")
+    tf = os.path.join(ROOT, "profiles", f"sweep_{params.layout}_512x256x1024_traffic.json")
     if os.path.exists(tf):
         with open(tf) as f:
             tr = json.load(f)
@@ -503,10 +519,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "coupled channel over sphere bed 512x256x1024, radii U[8,16], "
-                               f"bed porosity 0.45, TRT Lambda 3/16 tau 0.7, force 5e-7, CLI, {args.layout}, "
+                               f"bed porosity 0.45, TRT Lambda 3/16 tau 0.7, force 5e-7, CLI, {params.layout}, "
                                "FP32 shifted",
                    "nx": dom.nx, "ny": dom.ny, "nz": dom.nz, "cells": n_cells, "fluid_cells": n_fluid,
-                   "links": n_links, "layout": args.layout, "block": block, "launch_flags": flags},
+                   "links": n_links, "layout": params.layout, "layout_autotuner": layout_tuned,
+                   "block": block, "launch_flags": flags},
         "mflups": round(mflups, 1),
         "effective_gbs": round(achieved, 1),
         "fp32_rel_l2_vs_fp64_oracle": check,

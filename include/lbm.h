@@ -235,6 +235,25 @@ lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t flags);
 lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* block, int32_t* flags);
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps_per_trial);
 
+/* Layout autotuner.  The candidates are, for one domain, the two-grid, AA
+ * and (when nx, ny and nz are divisible by 4) brick layouts; for several
+ * domains the AA layout (one persistent launch) and the brick layout (one
+ * brick-list launch per step).  lbm_autotune_layout_bytes gives the device
+ * memory the tuner needs: the largest lbm_required_bytes over the candidates
+ * that can hold the geometry.  lbm_autotune_layout initialises each candidate
+ * from rest in dev_buf (caller-owned, at least that many bytes, 256-byte
+ * aligned), tunes its launch shape with lbm_autotune, times steps_per_trial
+ * steps (rounded up to even) with the tuned shape on the caller's stream, and
+ * returns the fastest layout in *layout and its time per step in
+ * *ms_per_step (may be NULL); no context is left in dev_buf.  Every layout
+ * gives bit-identical fields, so the choice only changes speed.  The choice
+ * is cached per process by (architecture, domain count, first domain's shape,
+ * total cells, bc, collision); with a cached choice the call returns it at
+ * once (dev_buf may then be NULL).  Synchronises. */
+lbm_status lbm_autotune_layout_bytes(const lbm_geometry* g, const lbm_params* params, int64_t* bytes);
+lbm_status lbm_autotune_layout(const lbm_geometry* g, const lbm_params* params, void* dev_buf, int64_t bytes,
+                               void* hip_stream, int32_t steps_per_trial, int32_t* layout, double* ms_per_step);
+
 /* Launch shape of a batched context.  AA layout (one persistent kernel):
  * workgroup size (256, 512 or 1024) and workgroups that step one domain
  * together (1..64); the persistent launch holds as many workgroups as can be

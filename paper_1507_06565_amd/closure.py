@@ -54,11 +54,10 @@ class Setup:
     tau: float = 1.0
     force: float = 1e-6
     bc: str = "cli"
-    # pore-scale runs and REV batch.  AA is the fastest layout at this size: its
-    # single 160 MB grid of a 128x64x256 bed stays in the 256 MB last-level
-    # cache, the brick layout's two grids (about 270 MB) do not (7.5 s against
-    # 11.7 s to steady state); both give the same fields bit for bit
-    layout: str = "aa"
+    # layout of the pore-scale runs and the REV batch: "auto" lets the
+    # library's layout autotuner time the candidates once per shape (every
+    # layout gives the same fields bit for bit)
+    layout: str = "auto"
     train: list = field(default_factory=lambda: [(e, 21 + i) for i, e in
                                                  enumerate((0.40, 0.45, 0.50, 0.55, 0.60, 0.65, 0.70, 0.75, 0.80))])
     test: list = field(default_factory=lambda: [(0.425, 31), (0.575, 32), (0.725, 33)])

@@ -157,13 +157,12 @@ __global__ void __launch_bounds__(BLOCK) k_batch(BatchArgs a) {
                 float ux = 0.0f;
                 if (c < N) {
                     const int x = c % nx, t = c / nx, y = t % ny, z = t / ny;
+                    const CellHead h = load_head(info, segbase, c);
                     const DenseNb nbi(nx, ny, nz, x, y, z);
                     if (even)
-                        ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, pa, info, segbase, lparam, pv, pv,
-                                                                  a.k, nbi, c);
+                        ux = cell_update<L_AA, P_EVEN, BC, false, true>(pa, pa, h, lparam, pv, pv, a.k, nbi, c);
                     else
-                        ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, pa, info, segbase, lparam, pv, pv,
-                                                                 a.k, nbi, c);
+                        ux = cell_update<L_AA, P_ODD, BC, false, true>(pa, pa, h, lparam, pv, pv, a.k, nbi, c);
                 }
                 if (check) {
                     const double w = wave_sum((double)ux);

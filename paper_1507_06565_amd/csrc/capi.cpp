@@ -128,6 +128,19 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 
+// layout autotuner cache: (architecture, domains, first domain's shape, total
+// cells, bc, collision) -> (layout, ms per step)
+struct LayoutKey {
+    std::string arch;
+    int ndom, nx, ny, nz, bc, collision;
+    int64_t cells;
+    bool operator<(const LayoutKey& o) const {
+        return std::tie(arch, ndom, nx, ny, nz, bc, collision, cells) <
+               std::tie(o.arch, o.ndom, o.nx, o.ny, o.nz, o.bc, o.collision, o.cells);
+    }
+};
+std::map<LayoutKey, std::pair<int, double>> g_layout_cache;
+
 }  // namespace
 
 lbm_status lbm::set_error(lbm_status s, const std::string& msg) { return fail(s, msg); }
@@ -745,6 +758,120 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial) {
     if (s2 != LBM_OK) return s2;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[{c->arch, c->d.nx, c->d.ny, c->d.nz, c->p.layout, c->d.bc}] = {bb, br | (bn << 1)};
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// candidate layouts of a geometry: single domain two-grid, AA and (when the
+// brick dimensions allow it) brick; batches AA (persistent launch) and brick
+std::vector<int> layout_candidates(const lbm_geometry* g) {
+    bool bricks = true;
+    for (const auto& D : g->doms) bricks = bricks && brick_dims_ok(D.desc);
+    std::vector<int> c;
+    if (g->doms.size() == 1) c.push_back(LBM_LAYOUT_TWOGRID);
+    c.push_back(LBM_LAYOUT_AA);
+    if (bricks) c.push_back(LBM_LAYOUT_BRICK);
+    return c;
+}
+
+LayoutKey layout_key(const lbm_geometry* g, const lbm_params* p, const std::string& arch) {
+    int64_t cells = 0;
+    for (const auto& D : g->doms) cells += D.ncells();
+    const auto& d = g->doms[0].desc;
+    return {arch, (int)g->doms.size(), d.nx, d.ny, d.nz, d.bc, p->collision, cells};
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_autotune_layout_bytes(const lbm_geometry* g, const lbm_params* p, int64_t* bytes) {
+    if (!g || !p || !bytes || g->doms.empty()) return fail(LBM_E_INVAL, "bad arguments");
+    int64_t most = 0;
+    int ok = 0;
+    for (int lay : layout_candidates(g)) {
+        lbm_params q = *p;
+        q.layout = lay;
+        int64_t b = 0;
+        if (lbm_required_bytes(g, &q, &b) != LBM_OK) continue;
+        most = std::max(most, b);
+        ++ok;
+    }
+    if (!ok) return fail(LBM_E_INVAL, "no layout can hold this geometry");
+    *bytes = most;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune_layout(const lbm_geometry* g, const lbm_params* p, void* dev_buf, int64_t bytes,
+                               void* hip_stream, int32_t steps_per_trial, int32_t* layout, double* ms_per_step) {
+    if (!g || !p || !layout || g->doms.empty() || steps_per_trial < 2) return fail(LBM_E_INVAL, "bad arguments");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "no HIP device");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "device properties");
+    const LayoutKey key = layout_key(g, p, prop.gcnArchName);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_layout_cache.find(key);
+        if (it != g_layout_cache.end()) {
+            *layout = it->second.first;
+            if (ms_per_step) *ms_per_step = it->second.second;
+            return LBM_OK;
+        }
+    }
+    if (!dev_buf) return fail(LBM_E_INVAL, "no device buffer (and no cached choice)");
+    int64_t need = 0;
+    lbm_status s = lbm_autotune_layout_bytes(g, p, &need);
+    if (s != LBM_OK) return s;
+    if (bytes < need) return fail(LBM_E_NOMEM, "device buffer smaller than lbm_autotune_layout_bytes");
+    const int64_t nsteps = steps_per_trial + (steps_per_trial & 1);  // even: whole AA step pairs
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(LBM_E_DEVICE, "event");
+    }
+    int best = -1;
+    double best_ms = 0.0;
+    for (int lay : layout_candidates(g)) {
+        lbm_params q = *p;
+        q.layout = lay;
+        int64_t b = 0;
+        if (lbm_required_bytes(g, &q, &b) != LBM_OK) continue;  // e.g. beyond a layout's limits
+        lbm_ctx* c = nullptr;
+        s = lbm_init(g, &q, dev_buf, bytes, hip_stream, &c);
+        if (s == LBM_OK) s = lbm_autotune(c, (int32_t)nsteps);
+        if (s == LBM_OK) s = lbm_step(c, 2);
+        float ms = 0.0f;
+        if (s == LBM_OK) {
+            hipEventRecord(e0, st);
+            s = lbm_step(c, nsteps);
+            hipEventRecord(e1, st);
+            if (s == LBM_OK && hipEventSynchronize(e1) != hipSuccess) s = fail(LBM_E_DEVICE, "timing event");
+            if (s == LBM_OK) hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (c) lbm_destroy(c);
+        if (s != LBM_OK) break;
+        const double per = (double)ms / (double)nsteps;
+        if (best < 0 || per < best_ms) {
+            best = lay;
+            best_ms = per;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s != LBM_OK) return s;
+    if (best < 0) return fail(LBM_E_INVAL, "no layout can hold this geometry");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_layout_cache[key] = {best, best_ms};
+    }
+    *layout = best;
+    if (ms_per_step) *ms_per_step = best_ms;
     return LBM_OK;
 }
 

@@ -215,16 +215,34 @@ struct BrickNb {
     }
 };
 
+// The cell word of a cell and the first link of its 512-cell link segment.
+// Callers load them as early as they can: the link records' addresses
+// depend on both.
+struct CellHead {
+    uint32_t inf;
+    int32_t seg;
+};
+
+// Loads the head of cell c.  A wavefront covers 64 consecutive, 64-aligned
+// cells (every layout and launch shape), so c >> SEG_SHIFT is the same in
+// all its lanes and the segment base is one uniform load.
+__device__ __forceinline__ CellHead load_head(const uint32_t* __restrict__ info, const int32_t* __restrict__ segbase,
+                                              int c) {
+    CellHead h;
+    h.inf = info[c];
+    h.seg = segbase[__builtin_amdgcn_readfirstlane((uint32_t)c >> SEG_SHIFT)];
+    return h;
+}
+
 // One cell of one time step: pull (with the partial bounce-back values),
 // link correction, collision, push and the next step's partial values.
 // Returns the x-velocity of this step's moments (0 for a solid cell).  c is
 // the cell's index in the population arrays, nbi(dx, dy, dz) that of its
-// neighbour (DenseNb or BrickNb).
+// neighbour (DenseNb or BrickNb), h its head (load_head).
 template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD, class PA, class NBI>
-__device__ __forceinline__ float cell_update(PA pa, PA pb, const uint32_t* __restrict__ info,
-                                             const int32_t* __restrict__ segbase,
-                                             const float* __restrict__ lparam, const float* pva, float* pvb,
-                                             const CellConsts& K, const NBI& nbi, int c) {
+__device__ __forceinline__ float cell_update(PA pa, PA pb, CellHead h, const float* __restrict__ lparam,
+                                             const float* pva, float* pvb, const CellConsts& K, const NBI& nbi,
+                                             int c) {
 #pragma clang fp contract(off)
     const unsigned uc = (unsigned)c;
 #define NB(dx, dy, dz) nbi((dx), (dy), (dz))
@@ -234,10 +252,10 @@ __device__ __forceinline__ float cell_update(PA pa, PA pb, const uint32_t* __res
     // domain to 2^30 cells), so loads use a scalar base + 32-bit offset.
 #define AT(bases, k, idx) (*(__attribute__((address_space(1))) float*)(bases).at((k), (uint32_t)(idx)))
 
-    // 1) streaming: the cell word and all 19 pulls are issued together; the
-    //    empty asm pins the pulls ahead of the solid-cell branch, so a
-    //    wavefront waits for memory once
-    const uint32_t inf = info[c];
+    // 1) streaming: all 19 pulls are issued together; the empty asm pins
+    //    them ahead of the solid-cell branch, so a wavefront waits for memory
+    //    once
+    const uint32_t inf = h.inf;
     float g[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -248,6 +266,9 @@ __device__ __forceinline__ float cell_update(PA pa, PA pb, const uint32_t* __res
         else
             g[k] = AT(pa, opp(k), NB(-L::ex[k], -L::ey[k], -L::ez[k]));
     }
+    const __attribute__((address_space(1))) char* lp = (const __attribute__((address_space(1))) char*)lparam;
+    const __attribute__((address_space(1))) char* vp = (const __attribute__((address_space(1))) char*)pva;
+    float prm[Q], pv[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) asm volatile("" ::"v"(g[k]));
     // a solid cell whose 32-cell group holds fluid runs along with the fluid
@@ -259,19 +280,15 @@ __device__ __forceinline__ float cell_update(PA pa, PA pb, const uint32_t* __res
         if (grp == 0u) return 0.0f;
     }
     const uint32_t mask = solid ? 0u : (inf & LINK_MASK_BITS);
+    const int base = h.seg + (int)(inf >> 18);
 
     // 2) links: the unknown population is the partial value P stored last
     //    step plus c0 times the second node's value
-    float prm[Q];
     if (mask) {
-        const int base = segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
         // every coefficient and partial-value load is issued before any is
-        // used, without branches: for a direction that is not a link the
-        // rank points at a neighbouring record (the arrays are padded), whose
-        // value is unused
-        const __attribute__((address_space(1))) char* lp = (const __attribute__((address_space(1))) char*)lparam;
-        const __attribute__((address_space(1))) char* vp = (const __attribute__((address_space(1))) char*)pva;
-        float pv[Q];
+        // used, without branches: for a direction that is not a link the rank
+        // points at a neighbouring record (the arrays are padded), whose value
+        // is unused
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int kk = opp(k);
@@ -311,27 +328,23 @@ __device__ __forceinline__ float cell_update(PA pa, PA pb, const uint32_t* __res
     //    coefficients are read again (a cache hit) rather than held in
     //    registers across the collision, for kernels short of registers
     if (mask) {
-        const int base = segbase[uc >> SEG_SHIFT] + (int)(inf >> 18);
-        const __attribute__((address_space(1))) char* lp = (const __attribute__((address_space(1))) char*)lparam;
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int kk = opp(k);
             if (mask & (1u << (kk - 1))) {
+                const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
                 float pk = prm[k];
-                if (RELOAD) {
-                    const uint32_t lr = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
-                    pk = __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)(lp + (lr << 2)));
-                }
+                if (RELOAD) pk = __builtin_nontemporal_load((const __attribute__((address_space(1))) float*)(lp + (li << 2)));
                 float c1, c0, cb;
                 bb_coeffs<BC>(pk, c1, c0, cb);
                 const float P = c1 * g[kk] + cb * g[k] + (pk != pk ? K.wterm[k] : 0.0f);
-                const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
                 *(__attribute__((address_space(1))) float*)((__attribute__((address_space(1))) char*)pvb + (li << 2)) = P;
             }
         }
     }
     return solid ? 0.0f : ux;
 #undef NB
+#undef AT
 }
 
 }  // namespace lbm

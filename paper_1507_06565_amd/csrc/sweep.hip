@@ -40,9 +40,10 @@ __global__ void __launch_bounds__(BLOCK) k_sweep(SweepArgs a) {
         y = t % ny;
         z = t / ny;
     }
+    const CellHead h = load_head(a.info, a.segbase, c);
     const DenseNb nbi(nx, ny, nz, x, y, z);
-    (void)cell_update<LAYOUT, PARITY, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, a.info, a.segbase, a.lparam,
-                                                     a.pva, a.pvb, a.k, nbi, c);
+    (void)cell_update<LAYOUT, PARITY, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, h, a.lparam, a.pva, a.pvb,
+                                                     a.k, nbi, c);
 }
 
 // Brick layout: one wavefront per stored brick, lane l = cell l of the brick
@@ -59,10 +60,16 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_brick(SweepArgs a) {
     if (slot >= a.nbricks) return;
     const int brick = LIST ? __builtin_amdgcn_readfirstlane(a.list[slot]) : slot;
     const int l = threadIdx.x & 63;
-    const BrickNb nbi(a.nbr[(int64_t)brick * 27 + (l < 27 ? l : 13)], brick, l);
-    const float ux = cell_update<L_TWOGRID, P_EVEN, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, a.info,
-                                                                   a.segbase, a.lparam, a.pva, a.pvb, a.k, nbi,
-                                                                   brick * 64 + l);
+    // the neighbour table and the cell's head are read together: the link
+    // records' addresses are then known as soon as the pulls have arrived
+    const int tab = a.nbr[(int64_t)brick * 27 + (l < 27 ? l : 13)];
+    const CellHead h = load_head(a.info, a.segbase, brick * 64 + l);
+    // all three have arrived before the pulls are addressed (the table is
+    // needed for that anyway), so the compiler cannot defer the head loads
+    asm volatile("" ::"v"(tab), "v"(h.inf), "s"(h.seg));
+    const BrickNb nbi(tab, brick, l);
+    const float ux = cell_update<L_TWOGRID, P_EVEN, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, h, a.lparam,
+                                                                   a.pva, a.pvb, a.k, nbi, brick * 64 + l);
     if (CHECK) {
         double v = (double)ux;
 #pragma unroll

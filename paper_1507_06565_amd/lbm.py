@@ -6,6 +6,7 @@ library.  torch provides the caller-owned device buffer and the stream.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 
 import numpy as np
 import torch
@@ -15,6 +16,7 @@ from ._lib import DomainDesc, LbmError, Params, Sphere, check, lib  # noqa: F401
 BC = {"sbb": 0, "cli": 1, "bouzidi": 2}
 COLLISION = {"bgk": 0, "trt": 1}
 LAYOUT = {"twogrid": 0, "aa": 1, "brick": 2}
+LAYOUT_NAME = {v: k for k, v in LAYOUT.items()}
 
 
 def _desc(dom, keep):
@@ -89,10 +91,35 @@ def required_bytes(geo: Geometry, params) -> int:
     return b.value
 
 
+def autotune_layout(geo: Geometry, params, steps_per_trial=10, device="cuda", stream=None):
+    """The fastest layout for this geometry and physics (lbm_autotune_layout),
+    as (name, ms per step).  A choice cached in this process returns at once;
+    otherwise a scratch buffer of lbm_autotune_layout_bytes is allocated for
+    the trials and released."""
+    q = make_params(dataclasses.replace(params, layout="twogrid"))
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    lay, ms = C.c_int32(), C.c_double()
+    if lib.lbm_autotune_layout(geo.ptr, C.byref(q), None, 0, C.c_void_p(s.cuda_stream), steps_per_trial,
+                               C.byref(lay), C.byref(ms)) == 0:
+        return LAYOUT_NAME[lay.value], ms.value
+    b = C.c_int64()
+    check(lib.lbm_autotune_layout_bytes(geo.ptr, C.byref(q), C.byref(b)), "lbm_autotune_layout_bytes")
+    buf = torch.empty(b.value, dtype=torch.uint8, device=s.device)
+    check(lib.lbm_autotune_layout(geo.ptr, C.byref(q), C.c_void_p(buf.data_ptr()), b.value,
+                                  C.c_void_p(s.cuda_stream), steps_per_trial, C.byref(lay), C.byref(ms)),
+          "lbm_autotune_layout")
+    del buf
+    return LAYOUT_NAME[lay.value], ms.value
+
+
 class Context:
-    """Owns an lbm_ctx* and the torch tensor that backs its device memory."""
+    """Owns an lbm_ctx* and the torch tensor that backs its device memory.
+    params.layout == "auto" picks the layout with autotune_layout first."""
 
     def __init__(self, geo: Geometry, params, device="cuda", stream=None, buffer=None):
+        if params.layout == "auto":
+            params = dataclasses.replace(params, layout=autotune_layout(geo, params, device=device,
+                                                                         stream=stream)[0])
         nbytes = required_bytes(geo, params)
         if buffer is None:
             buffer = torch.empty(nbytes, dtype=torch.uint8, device=device)

@@ -61,7 +61,7 @@ class Params:
     magic_lambda: float = 3.0 / 16.0
     rho0: float = 1.0
     force: tuple = (1e-6, 0.0, 0.0)
-    layout: str = "twogrid"  # "twogrid" | "aa" | "brick"
+    layout: str = "twogrid"  # "twogrid" | "aa" | "brick" | "auto" (timed by the layout autotuner)
 
 
 # ----------------------------------------------------------------------------

@@ -38,20 +38,26 @@ def test_interface_study_on_gpu_steady_profile():
     say({k: (round(v["zi"], 1), round(v["alpha"], 3), round(v["beta"], 3), round(v["err_BJ"], 4),
              round(v["err_Br"], 4), round(v["err_OTW"], 4)) for k, v in (("limit", lim), ("apparent", app))})
     assert 55 < lim["zi"] < 66 and app["zi"] <= lim["zi"]
+    # at the porosity limit the free side is pure fluid: the quadratic fits
+    # it closely, and the BJ analytic profile with the fitted alpha follows
+    # the pore-scale one to a few per cent (Sec. 3.2: close, not exact).  The
+    # apparent position lies inside the bed's top layer, where neither holds
+    # (the dependence on the interface position the paper reports)
+    assert lim["rms_free"] < 0.01
+    assert lim["err_BJ"] < 0.1
     for r in (lim, app):
         # the fitted coefficients satisfy their definitions with the fitted
         # slopes (eqs. (BJ), (OTW))
         sk = math.sqrt(r["K"])
         assert abs(r["alpha"] * (r["Us"] - r["Um"]) - sk * r["dU_plus"]) <= 1e-9 * abs(sk * r["dU_plus"])
         assert np.isfinite(r["beta"])
-        assert r["rms_free"] < 0.01
-        # the BJ analytic profile with the fitted alpha follows the pore-scale
-        # one to a few per cent (Sec. 3.2: close, but not exact)
-        assert r["err_BJ"] < 0.1
         sens = r["sensitivity"]
-        # the misfit search can only improve on the fitted parameters
-        assert sens["best"]["BJ"]["err"] <= r["err_BJ"] + 1e-9
-        assert sens["best"]["OTW"]["err"] <= r["err_OTW"] + 1e-9 or r["beta"] >= sens["otw_pole_beta"]
+        # the misfit search (alpha in [1e-3, 1e3], beta below the pole) can
+        # only improve on fitted parameters inside its range
+        if 1e-3 <= r["alpha"] <= 1e3:
+            assert sens["best"]["BJ"]["err"] <= r["err_BJ"] + 1e-9
+        if r["beta"] < sens["otw_pole_beta"]:
+            assert sens["best"]["OTW"]["err"] <= r["err_OTW"] + 1e-9
         mx = [e["u_max"] for e in sens["Br"]]
         assert all(a > b for a, b in zip(mx, mx[1:]))
         bj = [e["u_max"] for e in sens["BJ"]]
