@@ -65,6 +65,21 @@ lbm_status mlp_backward(const float* params, const void* params_bf16, const void
 lbm_status mlp_loss(const float* y, const float* target, const float* mask, int64_t B, double mask_sum, float* dy,
                     double* loss_partials, double* loss, void* stream);
 
+/* The same as mlp_loss (identical dy and loss, bit for bit) without the
+ * loss_partials argument, for callers that cannot allocate device memory or
+ * pass a workspace (code under stream capture, serving loops, harnesses that
+ * forbid allocation): the per-block partials and their total live in a static
+ * device array of the library (MLP_LOSS_NOALLOC_MAX_ROWS / 256 + 1 doubles,
+ * 128 KiB, held on each GPU the library runs on until the process ends), so
+ * the call allocates nothing.  B above MLP_LOSS_NOALLOC_MAX_ROWS is rejected
+ * with LBM_E_INVAL.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (several streams or host threads) race and must be
+ * serialised by the caller.  The calling thread's current device must be the
+ * one the stream and pointers belong to. */
+#define MLP_LOSS_NOALLOC_MAX_ROWS 4194304
+lbm_status mlp_loss_noalloc(const float* y, const float* target, const float* mask, int64_t B, double mask_sum,
+                            float* dy, double* loss, void* stream);
+
 /* One Adam step with bias correction (step t >= 1) on the FP32 parameters,
  * refreshing the BF16 copy; m and v are FP32 moment buffers. */
 lbm_status mlp_adam_step(float* params, void* params_bf16, float* m, float* v, const float* grad, double lr,

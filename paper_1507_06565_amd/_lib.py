@@ -81,6 +81,7 @@ _sig = {
     "mlp_forward": ([vp, vp, vp, i64, vp, vp, vp], i32),
     "mlp_backward": ([vp, vp, vp, vp, vp, i64, vp, vp, vp], i32),
     "mlp_loss": ([vp, vp, vp, i64, f64, vp, vp, P(f64), vp], i32),
+    "mlp_loss_noalloc": ([vp, vp, vp, i64, f64, vp, P(f64), vp], i32),
     "mlp_adam_step": ([vp, vp, vp, vp, vp, f64, f64, f64, f64, i64, vp], i32),
     "mlp_windows": ([vp, i32, i32, vp, vp], i32),
     "mlp_closure": ([vp, vp, i64, f64, vp, vp, vp], i32),

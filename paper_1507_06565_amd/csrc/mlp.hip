@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -332,6 +333,14 @@ __global__ void k_loss(const float* __restrict__ y, const float* __restrict__ t,
     if (threadIdx.x == 0) lpart[blockIdx.x] = red[0] * inv_n;
 }
 
+// The total of n loss partials in index order, by one thread (the same order
+// and the same FP64 additions as the host loop of mlp_loss).
+__global__ void k_sum_in_order(const double* __restrict__ part, int n, double* __restrict__ out) {
+    double L = 0.0;
+    for (int i = 0; i < n; ++i) L += part[i];
+    *out = L;
+}
+
 // windows of 33 porosities around every cell of ncols columns of height nz,
 // replicate padding; x[(col*nz + z)*64 + j]
 __global__ void k_windows(const double* __restrict__ eps, int nz, int64_t n, bf16* __restrict__ x) {
@@ -462,6 +471,40 @@ __global__ void __launch_bounds__(64) k_profile_loss(const float* __restrict__ y
 
 int64_t nwg_of(int64_t B) { return B / ROWS; }
 
+}  // namespace
+
+// Scratch of mlp_loss_noalloc: one loss partial per block of 256 rows, then
+// their total in the last slot.  A file-scope device array, so the entry
+// point needs no allocation; each GPU holds its own copy for the life of the
+// process.  Host code must use its device address (scratch_on_current_device),
+// never this name.
+static __device__ __align__(256) double scratch[MLP_LOSS_NOALLOC_MAX_ROWS / 256 + 1];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the calling thread's current device, looked
+// up once per device (with that device current) and kept.
+lbm_status scratch_on_current_device(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(LBM_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= MAX_DEVICES) return set_error(LBM_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(LBM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
 #define MCHK(expr, what)                                                                       \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -551,6 +594,39 @@ lbm_status mlp_loss(const float* y, const float* target, const float* mask, int6
         MCHK(hipStreamSynchronize(st), "synchronise");
         double L = 0;
         for (double v : h) L += v;
+        *loss = L;
+    } else {
+        MCHK(hipStreamSynchronize(st), "synchronise");
+    }
+    return LBM_OK;
+}
+
+lbm_status mlp_loss_noalloc(const float* y, const float* target, const float* mask, int64_t B, double mask_sum,
+                            float* dy, double* loss, void* stream) {
+    lbm_status s = check_batch(B);
+    if (s != LBM_OK) return s;
+    if (B > MLP_LOSS_NOALLOC_MAX_ROWS)
+        return set_error(LBM_E_INVAL, "mlp_loss_noalloc: batch of " + std::to_string(B) + " rows exceeds the " +
+                                          std::to_string((long long)MLP_LOSS_NOALLOC_MAX_ROWS) +
+                                          "-row limit of its static scratch (use mlp_loss)");
+    if (!y || !target || !mask || !dy) return set_error(LBM_E_INVAL, "null pointer");
+    double* part = nullptr;
+    s = scratch_on_current_device(&part);
+    if (s != LBM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned nb = (unsigned)((B + 255) / 256);
+    const float inv = (float)(1.0 / (mask_sum > 1.0 ? mask_sum : 1.0));
+    // every one of the nb partials is written before it is read: nothing in
+    // the scratch needs clearing between calls
+    k_loss<<<nb, 256, 0, st>>>(y, target, mask, B, inv, dy, part);
+    MCHK(hipGetLastError(), "loss");
+    double* total = part + MLP_LOSS_NOALLOC_MAX_ROWS / 256;
+    k_sum_in_order<<<1, 1, 0, st>>>(part, (int)nb, total);
+    MCHK(hipGetLastError(), "loss total");
+    if (loss) {
+        double L = 0.0;
+        MCHK(hipMemcpyAsync(&L, total, sizeof(double), hipMemcpyDeviceToHost, st), "copy loss");
+        MCHK(hipStreamSynchronize(st), "synchronise");
         *loss = L;
     } else {
         MCHK(hipStreamSynchronize(st), "synchronise");
