@@ -239,11 +239,17 @@ __device__ __forceinline__ CellHead load_head(const uint32_t* __restrict__ info,
 // Returns the x-velocity of this step's moments (0 for a solid cell).  c is
 // the cell's index in the population arrays, nbi(dx, dy, dz) that of its
 // neighbour (DenseNb or BrickNb), h its head (load_head).
-template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD, class PA, class NBI>
+//
+// MASKED (the head must already be in registers): a lane loads only the
+// pulls it uses; a solid lane, and a fluid lane for a direction whose source
+// is solid (a link: the pulled value is replaced by the partial value), load
+// nothing, so a wavefront does not fetch lines only such lanes would touch.
+template <int LAYOUT, int PARITY, int BC, bool NT, bool RELOAD, class PA, class NBI, bool MASKED = false>
 __device__ __forceinline__ float cell_update(PA pa, PA pb, CellHead h, const float* __restrict__ lparam,
                                              const float* pva, float* pvb, const CellConsts& K, const NBI& nbi,
                                              int c) {
 #pragma clang fp contract(off)
+    static_assert(!MASKED || LAYOUT == L_TWOGRID, "masked pulls exist for the pull layouts only");
     const unsigned uc = (unsigned)c;
 #define NB(dx, dy, dz) nbi((dx), (dy), (dz))
 
@@ -256,10 +262,20 @@ __device__ __forceinline__ float cell_update(PA pa, PA pb, CellHead h, const flo
     //    them ahead of the solid-cell branch, so a wavefront waits for memory
     //    once
     const uint32_t inf = h.inf;
+    // pulls a lane does not need (MASKED): none if solid, else the link ones
+    const uint32_t skip = inf == CELL_SOLID_WORD ? 0xFFFFFFFFu : (inf & LINK_MASK_BITS);
     float g[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-        if (LAYOUT == L_TWOGRID)
+        if (MASKED) {
+            // the source of pull k is x - e_k = x + e_opp(k): a link of x when
+            // bit opp(k) - 1 of the mask is set
+            const bool need = k == 0 ? skip != 0xFFFFFFFFu : !(skip & (1u << (opp(k) - 1)));
+            if (need)
+                g[k] = AT(pa, k, NB(-L::ex[k], -L::ey[k], -L::ez[k]));
+            else
+                g[k] = 0.0f;
+        } else if (LAYOUT == L_TWOGRID)
             g[k] = AT(pa, k, NB(-L::ex[k], -L::ey[k], -L::ez[k]));
         else if (PARITY == P_EVEN)
             g[k] = ld<NT>(&AT(pa, k, uc));

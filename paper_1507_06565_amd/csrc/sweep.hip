@@ -60,16 +60,18 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_brick(SweepArgs a) {
     if (slot >= a.nbricks) return;
     const int brick = LIST ? __builtin_amdgcn_readfirstlane(a.list[slot]) : slot;
     const int l = threadIdx.x & 63;
-    // the neighbour table and the cell's head are read together: the link
-    // records' addresses are then known as soon as the pulls have arrived
+    // the neighbour table and the cell's head are read together: each lane
+    // then issues only the pulls it uses (masked: none for a solid cell, and
+    // none across a link), and the link records' addresses are known as soon
+    // as the pulls have arrived
     const int tab = a.nbr[(int64_t)brick * 27 + (l < 27 ? l : 13)];
     const CellHead h = load_head(a.info, a.segbase, brick * 64 + l);
     // all three have arrived before the pulls are addressed (the table is
     // needed for that anyway), so the compiler cannot defer the head loads
     asm volatile("" ::"v"(tab), "v"(h.inf), "s"(h.seg));
     const BrickNb nbi(tab, brick, l);
-    const float ux = cell_update<L_TWOGRID, P_EVEN, BC, NT, false>(PopBases{a.pa}, PopBases{a.pb}, h, a.lparam,
-                                                                   a.pva, a.pvb, a.k, nbi, brick * 64 + l);
+    const float ux = cell_update<L_TWOGRID, P_EVEN, BC, NT, false, PopBases, BrickNb, true>(
+        PopBases{a.pa}, PopBases{a.pb}, h, a.lparam, a.pva, a.pvb, a.k, nbi, brick * 64 + l);
     if (CHECK) {
         double v = (double)ux;
 #pragma unroll

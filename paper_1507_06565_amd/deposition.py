@@ -337,13 +337,15 @@ def run_resolution(S_unit, D, Lx, Ly, free_height, re_target=2.0, tau=1.0, tol=1
 
 
 def grid_study(Ds=(4, 8, 16, 24, 32, 48), seed=11, Lx=4.0, Ly=4.0, n=64, free_height=3.0, re_target=2.0,
-               tau=1.0, re_tol=0.1, log=None):
+               tau=1.5, re_tol=0.1, log=None):
     """The grid study: one deposited packing (n spheres, diameters 50-150 %
     of the mean, in an Lx x Ly box of mean diameters) at each resolution D,
     at Re_D within re_tol of re_target (a second run with the force rescaled
     by the first run's Re_D if needed; Stokes flow scales linearly).  Returns
     per D the normalised profile and its relative L2 distance from the finest
-    resolution's and from the next finer one's."""
+    resolution's and from the next finer one's.  TRT with Lambda = 3/16 gives
+    steady Stokes fields independent of nu (Sec. 2.1), so a large tau (fast
+    diffusion to the steady state) changes only the run time."""
     S_unit = deposit(seed, Lx, Ly, n)
     res = []
     for D in Ds:
