@@ -273,14 +273,19 @@ def lattice_packing(S_unit, D, Lx, Ly):
     return S, nx, ny
 
 
+def channel_height(S_unit, free_height):
+    """Height between the wall planes in mean diameters: the bed top plus the
+    free channel, rounded up to a whole number so that every resolution D
+    has the same height H = T D cells."""
+    return int(math.ceil(bed_height(S_unit) + free_height))
+
+
 def study_domain(S_unit, D, Lx, Ly, free_height, bc="cli"):
     """Channel over the deposited bed at resolution D: periodic x and y, wall
-    layers at z = 0 and the top; the free channel above the bed top is
-    free_height mean diameters high."""
+    layers at z = 0 and z = T D + 1 (T = channel_height), so the fluid height
+    between the wall planes is exactly T D cells at every D."""
     S, nx, ny = lattice_packing(S_unit, D, Lx, Ly)
-    top = bed_height(S_unit) + free_height
-    nz = int(math.ceil(top * D)) + 2
-    nz += (-nz) % 4  # brick layouts need multiples of 4
+    nz = channel_height(S_unit, free_height) * D + 2
     return W.Domain(nx, ny, nz, spheres=S, bc=bc, name=f"deposit-D{D}")
 
 
@@ -301,7 +306,7 @@ def normalised_profile(u, npts=401):
 
 
 def run_resolution(S_unit, D, Lx, Ly, free_height, re_target=2.0, tau=1.0, tol=1e-7, check=100,
-                   chunk=50_000, max_steps=4_000_000, layout="auto", G=None):
+                   chunk=50_000, max_steps=4_000_000, layout="auto", G=None, log=None):
     """One resolution of the study: the channel over the unit packing at D
     cells per mean diameter, driven by a body force G along x chosen for
     Re_D = U_max D / nu = re_target (from a plane-channel estimate over the
@@ -328,6 +333,8 @@ def run_resolution(S_unit, D, Lx, Ly, free_height, re_target=2.0, tau=1.0, tol=1
         steps += n
         if n < chunk:
             break
+        if log:
+            log(f"  D = {D}: {steps} steps ({time.perf_counter() - t0:.0f} s)")
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     u, _, por = ctx.average_profile()
@@ -348,10 +355,19 @@ def grid_study(Ds=(4, 8, 16, 24, 32, 48), seed=11, Lx=4.0, Ly=4.0, n=64, free_he
     diffusion to the steady state) changes only the run time."""
     S_unit = deposit(seed, Lx, Ly, n)
     res = []
+    G_next = None
     for D in Ds:
-        r = run_resolution(S_unit, D, Lx, Ly, free_height, re_target, tau)
+        r = run_resolution(S_unit, D, Lx, Ly, free_height, re_target, tau, G=G_next, log=log)
         if abs(r["Re_D"] / re_target - 1.0) > re_tol:
-            r = run_resolution(S_unit, D, Lx, Ly, free_height, re_target, tau, G=r["G"] * re_target / r["Re_D"])
+            if log:
+                log(f"D = {D}: Re_D {r['Re_D']:.3f}, rerun with the force rescaled")
+            r = run_resolution(S_unit, D, Lx, Ly, free_height, re_target, tau, G=r["G"] * re_target / r["Re_D"],
+                               log=log)
+        # at fixed nu and geometry in units of D, Re_D grows as G D^3: the next
+        # resolution's force
+        G_next = None
+        if D != Ds[-1]:
+            G_next = r["G"] * (re_target / r["Re_D"]) * (D / Ds[Ds.index(D) + 1]) ** 3
         s, un = normalised_profile(r["u"])
         r["s"], r["u_norm"] = s, un
         if log:

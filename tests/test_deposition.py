@@ -90,8 +90,8 @@ def test_narrow_box_is_refused():
 def test_lattice_packing_exact(packing, D):
     """Scaled to D cells per mean diameter and quantised: dyadic, exactly
     non-overlapping with periodic images, centres inside the periodic box,
-    resting on the bottom wall plane z = 0.5; the study domain's height is a
-    multiple of 4 (brick layout) above bed and free channel."""
+    resting on the bottom wall plane z = 0.5; the study domain's fluid height
+    is the same whole number of mean diameters at every D."""
     S, nx, ny = Dp.lattice_packing(packing, D, LX, LY)
     assert (nx, ny) == (4 * D, 4 * D)
     assert np.array_equal(S, W.quantise(S))
@@ -99,7 +99,8 @@ def test_lattice_packing_exact(packing, D):
     assert np.all((S[:, 0] >= 0) & (S[:, 0] < nx) & (S[:, 1] >= 0) & (S[:, 1] < ny))
     assert np.all(S[:, 2] - S[:, 3] >= 0.5 - 2.0 ** -11)
     d = Dp.study_domain(packing, D, LX, LY, 3.0)
-    assert d.nz % 4 == 0 and d.nz >= (Dp.bed_height(packing) + 3.0) * D + 2
+    T = Dp.channel_height(packing, 3.0)
+    assert d.nz == T * D + 2 and T >= Dp.bed_height(packing) + 3.0
 
 
 def test_normalised_profile():
