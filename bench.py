@@ -305,6 +305,60 @@ def rev_cpu_baseline(doms, params, budget_s=15.0):
             "sample": f"one 48^3 REV cube of the batch ({d.name}), {nsteps} steps, FP64 two-grid, {dt:.1f} s"}
 
 
+def weak_block(args):
+    """The paper's weak-scaling block shape on one GPU (Sec. 3, the MLUPS-per-
+    core figure: one 151^3 block with one sphere of diameter 90 per core, TRT):
+    4 x 4 x 4 such blocks, 604^3 cells, periodic on every axis, body force
+    along x, brick layout; the same run with simple and with central linear
+    interpolated bounce-back, for the cost of CLI over SBB (the paper reports
+    about 10 % on its CPU cluster)."""
+    import numpy as np
+    import torch
+
+    from paper_1507_06565_amd import lbm, workloads as W
+
+    n, B = 4, 151
+    L = n * B
+    c = np.array([(i + 0.5) * B for i in range(n)])
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    # centres off the lattice points by dyadic fractions, radius 45
+    S = W.quantise(np.column_stack([X.ravel() + 0.25, Y.ravel() + 0.125, Z.ravel() + 0.375,
+                                    np.full(X.size, 45.0)]))
+    torch.cuda.set_device(0)
+    out = {}
+    for bc in ("sbb", "cli"):
+        d = W.Domain(L, L, L, periodic=(1, 1, 1), wall_lo=(0, 0, 0), wall_hi=(0, 0, 0), spheres=S, bc=bc,
+                     name=f"weak-block-{bc}")
+        p = W.Params(collision="trt", tau_plus=0.7, magic_lambda=3.0 / 16.0, force=(1e-6, 0.0, 0.0),
+                     layout="brick")
+        t0 = time.perf_counter()
+        geo = lbm.Geometry(d)
+        _, n_fluid, n_links = geo.info()
+        ctx = lbm.Context(geo, p)
+        block, flags = ctx.autotune(6)
+        log(f"{bc}: {L}^3, {n_fluid} fluid cells, {n_links} links, launch ({block}, {flags}) "
+            f"({time.perf_counter() - t0:.1f} s)")
+        ctx.step(args.warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.step(args.steps)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out[bc] = {"ms_per_step": round(ms, 4), "mlups": round(L ** 3 / (ms * 1e-3) / 1e6, 1),
+                   "fluid_cells": n_fluid, "links": n_links, "block": block, "flags": flags}
+        log(f"{bc}: {ms:.4f} ms per step")
+        del ctx, geo
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "4x4x4 blocks of 151^3, one sphere of diameter 90 each (604^3), TRT "
+                      "Lambda 3/16 tau 0.7, periodic, brick layout", "steps": args.steps, "warmup": args.warmup,
+                      "sbb": out["sbb"], "cli": out["cli"],
+                      "cli_over_sbb": round(out["cli"]["ms_per_step"] / out["sbb"]["ms_per_step"], 4)}),
+          flush=True)
+
+
 def closure_kernels(args):
     """Speed of the learned-closure kernels: BF16 MFMA forward and backward of
     the closure network on B rows, the closure map, and the gray column (one
@@ -391,9 +445,10 @@ def main():
                          "rev-batch BLOCK,WORKGROUPS_PER_SAMPLE")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("bed", "rev-batch", "closure-kernels"), default="bed",
+    ap.add_argument("--workload", choices=("bed", "rev-batch", "closure-kernels", "weak-block"), default="bed",
                     help="bed: the large coupled domain (default); rev-batch: the batched REV cubes; "
-                         "closure-kernels: closure network and gray column speed")
+                         "closure-kernels: closure network and gray column speed; weak-block: the paper's "
+                         "weak-scaling block shape, SBB against CLI")
     ap.add_argument("--samples", type=int, default=512, help="rev-batch: number of cubes")
     ap.add_argument("--chunk", type=int, default=2000, help="rev-batch: steps per persistent launch")
     ap.add_argument("--max-steps", type=int, default=2_000_000, help="rev-batch: cap per sample")
@@ -413,6 +468,9 @@ def main():
         return
     if args.workload == "closure-kernels":
         closure_kernels(args)
+        return
+    if args.workload == "weak-block":
+        weak_block(args)
         return
 
     import numpy as np
@@ -497,7 +555,8 @@ def main():
     if os.path.exists(tf):
         with open(tf) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_hash") == _sweep_hash():
+        # counted bytes apply only to the same kernel sources and launch shape
+        if tr.get("kernel_source_hash") == _sweep_hash() and tr.get("launch") == f"{block},{flags}":
             traffic = tr.get("bytes_per_launch")
 
     cpu = None
@@ -531,7 +590,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg,
-                     # counter bytes (FETCH_SIZE + WRITE_SIZE, copy-calibrated) over this run's time per launch
+                     # counted bytes (read and write requests by size at the L2-fabric interface)
+                     # over this run's time per launch
                      "traffic_gbs": round(traffic / (ms_per_step * 1e-3) / 1e9, 1) if traffic else None},
         "cpu_baseline": cpu,
     }
