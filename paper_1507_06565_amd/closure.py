@@ -320,13 +320,41 @@ def experiment(s: Setup, init_seed=0):
             "params": net.params.cpu().numpy(), "total_seconds": time.perf_counter() - t_all}
 
 
+def evaluate_at_height(params, s: Setup, nz, C_kc, beds=None):
+    """The trained closure (network parameters `params`) on held-out beds of
+    another height: the same lateral size, grain sizes and physics, nz layers
+    with the bed in the lower half, so the gray column is 1 x 1 x nz.  The
+    network is local (33-cell porosity windows), so a closure trained on one
+    bed height applies to any."""
+    import dataclasses
+
+    se = dataclasses.replace(s, nz=nz, bed_top=nz // 2)
+    net = mlp.ClosureNet(params)
+    out = []
+    for e, seed in (beds or s.test):
+        b = run_bed(se, e, seed)
+        r = evaluate(net, b, se, C_kc)
+        log(f"bed {se.nx}x{se.ny}x{nz} eps {e} seed {seed}: learned {r['learned_err']:.4f}, "
+            f"nu/eps {r['baseline_nu_over_eps_err']:.4f}, nu {r['baseline_nu_err']:.4f}; "
+            f"pore scale {r['pore_scale_seconds']:.2f} s ({r['pore_scale_steps']} steps) vs gray+MLP "
+            f"{r['gray_seconds'] + r['mlp_seconds']:.4f} s (x{r['cost_ratio']:.0f})")
+        out.append(r)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--small", action="store_true", help="the scaled-down experiment")
+    ap.add_argument("--eval-nz", type=int, default=0,
+                    help="also evaluate the trained closure on held-out beds of this height (1 x 1 x nz columns)")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     args = ap.parse_args()
     s = small_setup() if args.small else Setup()
     res = experiment(s)
+    if args.eval_nz:
+        hs = evaluate_at_height(res["params"], s, args.eval_nz, res["kozeny_carman_C"])
+        res["held_out_nz"] = [{k: v for k, v in r.items() if not k.startswith("u_")} for r in hs]
+        res["eval_nz"] = args.eval_nz
     res.pop("params")
     line = {k: v for k, v in res.items() if k != "held_out"}
     line["held_out"] = [{k: v for k, v in r.items() if not k.startswith("u_")} for r in res["held_out"]]
