@@ -20,12 +20,15 @@
 // (1 - omega-/2).  Optional wall layers at z = 0 and z = nz-1 (half-way
 // bounce-back; the top wall may move, Ladd's correction).
 //
-// One workgroup per column, one thread per cell, the whole state resident in
-// LDS (19 * nz floats, 38 KB for nz = 512), the time loop inside the kernel;
-// global memory is touched only to load and store the state and to write the
-// final profile.  The steady-state test (relative change of the FP64 sum of
-// u_x over check_every steps) is evaluated in the kernel with a fixed-order
-// workgroup reduction.
+// One workgroup per column, one thread per cell, the time loop inside the
+// kernel.  The nine populations with e_z = 0 never leave their cell in a
+// 1 x 1 periodic column, so they stay in registers; the ten with e_z != 0
+// pass through two LDS buffers (read one, write the other: one barrier per
+// step), each thread pulling from offsets it computes once, wall bounce-back
+// included.  Global memory is touched only to load and store the state and to
+// write the final profile.  The steady-state test (relative change of the
+// FP64 sum of u_x over check_every steps) is evaluated in the kernel with a
+// fixed-order workgroup reduction.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -46,7 +49,7 @@ struct GrayArgs {
     int64_t* steps;       // per column
     double* uprev;        // per column
     int32_t* status;      // per column: 0 running, 1 converged, -1 unstable
-    int32_t nz, walls, steady, check_every;
+    int32_t nz, walls, steady, check_every, lid;
     int64_t nsteps;
     double tol;
     float rho0, G[3];
@@ -57,137 +60,223 @@ namespace {
 
 using L = D3Q19;
 
+// the populations with e_z != 0; slot m holds direction MOVK[m], and
+// opposite directions sit in slots m and m ^ 1
+constexpr int NMOV = 10;
+__device__ constexpr int MOVK[NMOV] = {5, 6, 11, 12, 13, 14, 15, 16, 17, 18};
+
+// per-cell constants of the collision
+struct GrayCell {
+    float D, phi, wp, wm, cmi, hwp, hwm, omwp, A, c45, c9, m15wp, m3cpl, den;
+    float Ge[3], hGe[3];
+};
+
 template <int BLOCK>
+struct GrayShared {
+    float mv[2][NMOV][BLOCK];  // moving populations, two buffers
+    double red[BLOCK / 64];    // one partial sum per wavefront
+    int stop;
+};
+
+// One pull-collide step of every active cell of the column: pull the moving
+// populations from buffer B, collide all 19 in registers, write the moving
+// post-collision values to buffer 1 - B at the cell itself.
+template <int BLOCK, bool FORCH, int B>
+__device__ __forceinline__ void gray_step(GrayShared<BLOCK>& sh, float (&g)[Q], const int (&src)[NMOV],
+                                          const float (&add)[NMOV], bool lid, const GrayCell& c, float rho_inv,
+                                          float w3r_axis, float w3r_edge, int z, float& ux, float& uy, float& uz) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int m = 0; m < NMOV; ++m) g[MOVK[m]] = (&sh.mv[B][0][0])[src[m]];
+    if (lid) {
+#pragma unroll
+        for (int m = 0; m < NMOV; ++m) g[MOVK[m]] += add[m];
+    }
+    float gp2[9], gm2[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        gp2[p] = g[2 * p + 1] + g[2 * p + 2];
+        gm2[p] = g[2 * p + 1] - g[2 * p + 2];
+    }
+    float drho = g[0], jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int k = 2 * p + 1;
+        drho += gp2[p];
+        if (L::ex[k] > 0) jx += gm2[p];
+        if (L::ex[k] < 0) jx -= gm2[p];
+        if (L::ey[k] > 0) jy += gm2[p];
+        if (L::ey[k] < 0) jy -= gm2[p];
+        if (L::ez[k] > 0) jz += gm2[p];
+        if (L::ez[k] < 0) jz -= gm2[p];
+    }
+    const float vx = fmaf(jx, rho_inv, c.hGe[0]), vy = fmaf(jy, rho_inv, c.hGe[1]), vz = fmaf(jz, rho_inv, c.hGe[2]);
+    float den = c.den;
+    if (FORCH && c.phi != 0.0f) {
+        const float c0 = 0.5f * (1.0f + 0.5f * c.D), c1 = 0.5f * c.phi;
+        const float vn = sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+        den = 1.0f / (c0 + sqrtf(fmaf(c0, c0, c1 * vn)));
+    }
+    ux = vx * den;
+    uy = vy * den;
+    uz = vz * den;
+    float Fx = fmaf(-c.D, ux, c.Ge[0]), Fy = fmaf(-c.D, uy, c.Ge[1]), Fz = fmaf(-c.D, uz, c.Ge[2]);
+    const float uu = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+    if (FORCH && c.phi != 0.0f) {
+        const float pu = c.phi * sqrtf(uu);
+        Fx = fmaf(-pu, ux, Fx);
+        Fy = fmaf(-pu, uy, Fy);
+        Fz = fmaf(-pu, uz, Fz);
+    }
+    const float uF = fmaf(ux, Fx, fmaf(uy, Fy, uz * Fz));
+    // even part: dp = -wp gp + w [T0 + A (e.u (4.5 wp e.u + 9 cpl e.F) + T1)]
+    // odd part:  dm = -wm gm + 3 rho0 w (wm e.u + cmi e.F)
+    const float T0 = c.wp * drho;
+    const float T1 = fmaf(c.m15wp, uu, c.m3cpl * uF);
+    g[0] = fmaf(c.omwp, g[0], fmaf(c.A, T1, T0) * (1.0f / 3.0f));
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int k = 2 * p + 1;
+        const float w = (float)weight(k);
+        const float w3r = norm2(k) == 1 ? w3r_axis : w3r_edge;
+        float eu = 0.0f, eF = 0.0f;
+        if (L::ex[k]) { eu = L::ex[k] > 0 ? ux : -ux; eF = L::ex[k] > 0 ? Fx : -Fx; }
+        if (L::ey[k]) {
+            eu = L::ex[k] ? (L::ey[k] > 0 ? eu + uy : eu - uy) : (L::ey[k] > 0 ? uy : -uy);
+            eF = L::ex[k] ? (L::ey[k] > 0 ? eF + Fy : eF - Fy) : (L::ey[k] > 0 ? Fy : -Fy);
+        }
+        if (L::ez[k]) {
+            const bool first = !L::ex[k] && !L::ey[k];
+            eu = first ? (L::ez[k] > 0 ? uz : -uz) : (L::ez[k] > 0 ? eu + uz : eu - uz);
+            eF = first ? (L::ez[k] > 0 ? Fz : -Fz) : (L::ez[k] > 0 ? eF + Fz : eF - Fz);
+        }
+        const float X = fmaf(c.c45, eu, c.c9 * eF);
+        const float Z = fmaf(c.A, fmaf(eu, X, T1), T0);
+        const float dp = fmaf(-c.hwp, gp2[p], w * Z);
+        const float dm = fmaf(-c.hwm, gm2[p], w3r * fmaf(c.wm, eu, c.cmi * eF));
+        g[k] = (g[k] + dp) + dm;
+        g[k + 1] = (g[k + 1] + dp) - dm;
+    }
+#pragma unroll
+    for (int m = 0; m < NMOV; ++m) sh.mv[1 - B][m][z] = g[MOVK[m]];
+}
+
+template <int BLOCK, bool FORCH>
 __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
 #pragma clang fp contract(off)
-    extern __shared__ float lds[];  // Q * nz populations
-    __shared__ double red[BLOCK];
-    __shared__ int s_stop;
+    __shared__ GrayShared<BLOCK> sh;
     const int col = blockIdx.x;
     const int z = threadIdx.x;
     const int nz = a.nz;
     const bool live = z < nz;
-    const bool solid = a.walls && (z == 0 || z == nz - 1);
+    const bool active = live && !(a.walls && (z == 0 || z == nz - 1));
     float* gs = a.state + (int64_t)col * Q * nz;
-    float eps = 1.0f, wp = 1.0f, wm = 1.0f, D = 0.0f, phi = 0.0f;
-    if (live) {
-        const float* cp = a.cell + ((int64_t)col * nz + z) * 4;
-        eps = cp[0]; wp = cp[1]; wm = cp[2]; D = cp[3];
-        if (a.phi) phi = a.phi[(int64_t)col * nz + z];
+    float g[Q];
+    GrayCell c{};
+    {
+        float eps = 1.0f, wp = 1.0f, wm = 1.0f, D = 0.0f;
+        if (live) {
+            const float* cp = a.cell + ((int64_t)col * nz + z) * 4;
+            eps = cp[0]; wp = cp[1]; wm = cp[2]; D = cp[3];
+            if (FORCH) c.phi = a.phi[(int64_t)col * nz + z];
+        }
 #pragma unroll
-        for (int k = 0; k < Q; ++k) lds[k * nz + z] = gs[k * nz + z];
+        for (int k = 0; k < Q; ++k) g[k] = live ? gs[k * nz + z] : 0.0f;
+        const float cpl = 1.0f - 0.5f * wp;
+        c.D = D;
+        c.wp = wp;
+        c.wm = wm;
+        c.cmi = 1.0f - 0.5f * wm;
+        c.hwp = 0.5f * wp;
+        c.hwm = 0.5f * wm;
+        c.omwp = 1.0f - wp;
+        c.A = a.rho0 * (1.0f / eps);
+        c.c45 = 4.5f * wp;
+        c.c9 = 9.0f * cpl;
+        c.m15wp = -1.5f * wp;
+        c.m3cpl = -3.0f * cpl;
+        c.den = 1.0f / (1.0f + 0.5f * D);
+        for (int i = 0; i < 3; ++i) {
+            c.Ge[i] = eps * a.G[i];
+            c.hGe[i] = 0.5f * c.Ge[i];
+        }
     }
-    const float inv_eps = 1.0f / eps;
-    const float cpl = 1.0f - 0.5f * wp, cmi = 1.0f - 0.5f * wm;
-    const float Ge[3] = {eps * a.G[0], eps * a.G[1], eps * a.G[2]};
+    // pull sources of the moving populations: the neighbour cell (periodic
+    // in z), or this cell's opposite population where the neighbour is a wall
+    // layer (half-way bounce-back, plus the moving-wall term at the top)
+    int src[NMOV];
+    float add[NMOV];
+#pragma unroll
+    for (int m = 0; m < NMOV; ++m) {
+        const int k = MOVK[m];
+        int zs = z - L::ez[k];
+        add[m] = 0.0f;
+        if (!active) {
+            src[m] = m * BLOCK + z;
+        } else if (a.walls && (zs == 0 || zs == nz - 1)) {
+            src[m] = (m ^ 1) * BLOCK + z;
+            if (zs == nz - 1) add[m] = a.wterm[k];
+        } else {
+            zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
+            src[m] = m * BLOCK + zs;
+        }
+        sh.mv[0][m][z] = g[k];
+    }
+    const bool lid = a.lid != 0;
+    const float rho_inv = 1.0f / a.rho0;
+    const float w3r_axis = 3.0f * a.rho0 * (float)(1.0 / 18.0), w3r_edge = 3.0f * a.rho0 * (float)(1.0 / 36.0);
     float ux = 0.0f, uy = 0.0f, uz = 0.0f;
     const int64_t s0 = a.steps[col];
     int64_t s = s0;
+    int until_check = a.check_every;
     bool stop = a.nsteps <= 0 || (a.steady && a.status[col] != 0);
-    while (!stop) {
-        __syncthreads();
-        float g[Q];
-        if (live && !solid) {
-#pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                int zs = z - L::ez[k];
-                if (a.walls && (zs == 0 || zs == nz - 1)) {
-                    // half-way bounce-back from a wall layer
-                    g[k] = lds[opp(k) * nz + z] + (zs == nz - 1 ? a.wterm[k] : 0.0f);
-                } else {
-                    zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
-                    g[k] = lds[k * nz + zs];
-                }
-            }
-        }
-        __syncthreads();
-        if (live && !solid) {
-            float drho = g[0], jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-            for (int p = 0; p < 9; ++p) {
-                const int k = 2 * p + 1;
-                const float sm = g[k] + g[k + 1], df = g[k] - g[k + 1];
-                drho += sm;
-                if (L::ex[k]) jx += L::ex[k] * df;
-                if (L::ey[k]) jy += L::ey[k] * df;
-                if (L::ez[k]) jz += L::ez[k] * df;
-            }
-            const float r = 1.0f / a.rho0;
-            const float vx = jx * r + 0.5f * Ge[0], vy = jy * r + 0.5f * Ge[1], vz = jz * r + 0.5f * Ge[2];
-            float den = 1.0f / (1.0f + 0.5f * D);
-            if (phi != 0.0f) {
-                const float c0 = 0.5f * (1.0f + 0.5f * D), c1 = 0.5f * phi;
-                const float vn = sqrtf(vx * vx + vy * vy + vz * vz);
-                den = 1.0f / (c0 + sqrtf(c0 * c0 + c1 * vn));
-            }
-            ux = vx * den;
-            uy = vy * den;
-            uz = vz * den;
-            float Fx = -D * ux + Ge[0], Fy = -D * uy + Ge[1], Fz = -D * uz + Ge[2];
-            if (phi != 0.0f) {
-                const float pu = phi * sqrtf(ux * ux + uy * uy + uz * uz);
-                Fx = Fx - pu * ux;
-                Fy = Fy - pu * uy;
-                Fz = Fz - pu * uz;
-            }
-            const float uu = ux * ux + uy * uy + uz * uz;
-            const float uF = ux * Fx + uy * Fy + uz * Fz;
-            {
-                const float w0 = 1.0f / 3.0f;
-                const float eq = w0 * (drho - 1.5f * a.rho0 * uu * inv_eps);
-                const float src = w0 * a.rho0 * (-3.0f * uF * inv_eps);
-                lds[z] = g[0] - wp * (g[0] - eq) + cpl * src;
-            }
-#pragma unroll
-            for (int p = 0; p < 9; ++p) {
-                const int k = 2 * p + 1;
-                const float w = (float)weight(k);
-                const float eu = L::ex[k] * ux + L::ey[k] * uy + L::ez[k] * uz;
-                const float eF = L::ex[k] * Fx + L::ey[k] * Fy + L::ez[k] * Fz;
-                const float eqp = w * (drho + a.rho0 * (4.5f * eu * eu * inv_eps - 1.5f * uu * inv_eps));
-                const float eqm = w * (3.0f * a.rho0 * eu);
-                const float sp = w * a.rho0 * (9.0f * eu * eF * inv_eps - 3.0f * uF * inv_eps);
-                const float smn = w * a.rho0 * (3.0f * eF);
-                const float gp = 0.5f * (g[k] + g[k + 1]);
-                const float gm = 0.5f * (g[k] - g[k + 1]);
-                const float dp = -wp * (gp - eqp) + cpl * sp;
-                const float dm = -wm * (gm - eqm) + cmi * smn;
-                lds[k * nz + z] = g[k] + dp + dm;
-                lds[(k + 1) * nz + z] = g[k + 1] + dp - dm;
-            }
-        } else if (live) {
-            ux = uy = uz = 0.0f;
-        }
+    __syncthreads();
+    // after each step: the barrier that orders this step's writes before the
+    // next step's reads, and, every check_every steps, the steady-state test
+    // on the FP64 sum of u_x (per-wavefront butterflies, then the wavefront
+    // sums in order)
+    auto finish = [&]() {
         ++s;
         stop = s - s0 >= a.nsteps;
-        if (a.steady && ((s - s0) % a.check_every == 0)) {
-            red[threadIdx.x] = (live && !solid) ? (double)ux : 0.0;
+        if (a.steady && --until_check == 0) {
+            until_check = a.check_every;
+            double v = active ? (double)ux : 0.0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if ((z & 63) == 0) sh.red[z >> 6] = v;
             __syncthreads();
-            for (int w = BLOCK / 2; w > 0; w >>= 1) {
-                if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                const double U = red[0], Up = a.uprev[col];
+            if (z == 0) {
+                double U = 0.0;
+                for (int w = 0; w < BLOCK / 64; ++w) U += sh.red[w];
+                const double Up = a.uprev[col];
                 int st = 0;
                 if (!(fabs(U) < 0.4 * nz)) st = -1;
                 else if (fabs(U - Up) <= a.tol * fabs(U)) st = 1;
                 a.uprev[col] = U;
                 if (st != 0) a.status[col] = st;
-                s_stop = st;
+                sh.stop = st;
             }
             __syncthreads();
-            if (s_stop != 0) stop = true;
+            if (sh.stop != 0) stop = true;
+        } else {
+            __syncthreads();
         }
+    };
+    while (!stop) {
+        if (active) gray_step<BLOCK, FORCH, 0>(sh, g, src, add, lid, c, rho_inv, w3r_axis, w3r_edge, z, ux, uy, uz);
+        finish();
+        if (stop) break;
+        if (active) gray_step<BLOCK, FORCH, 1>(sh, g, src, add, lid, c, rho_inv, w3r_axis, w3r_edge, z, ux, uy, uz);
+        finish();
     }
-    __syncthreads();
+    // every thread holds its own cell's post-collision populations
     if (live) {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) gs[k * nz + z] = lds[k * nz + z];
+        for (int k = 0; k < Q; ++k) gs[k * nz + z] = g[k];
         double* uo = a.u + ((int64_t)col * nz + z) * 3;
         uo[0] = ux; uo[1] = uy; uo[2] = uz;
     }
-    if (threadIdx.x == 0) a.steps[col] = s;
+    if (z == 0) a.steps[col] = s;
 }
 
 int64_t align_up(int64_t v, int64_t al) { return (v + al - 1) / al * al; }
@@ -257,10 +346,14 @@ lbm_status upload_cells(gray_ctx* c, const double* eps, const double* nu_eff, co
 
 lbm_status launch(gray_ctx* c) {
     const int block = (int)align_up(c->nz, 64);
-    const size_t lds = (size_t)Q * c->nz * 4;
+    const bool forch = c->args.phi != nullptr;
     hipError_t e;
     switch (block) {
-#define GB(B) case B: k_gray<B><<<c->ncols, B, lds, c->stream>>>(c->args); break;
+#define GB(B)                                                                       \
+    case B:                                                                         \
+        if (forch) k_gray<B, true><<<c->ncols, B, 0, c->stream>>>(c->args);         \
+        else k_gray<B, false><<<c->ncols, B, 0, c->stream>>>(c->args);              \
+        break;
         GB(64) GB(128) GB(192) GB(256) GB(320) GB(384) GB(448) GB(512) GB(576) GB(640) GB(704)
 #undef GB
         default: return set_error(LBM_E_INVAL, "column height must be at most 704");
@@ -279,8 +372,9 @@ lbm_status launch(gray_ctx* c) {
 extern "C" {
 
 lbm_status gray_required_bytes(int32_t ncols, int32_t nz, int64_t* bytes) {
-    // the column (19 * nz floats) and the reduction buffer must fit the 64 KB
-    // of LDS a workgroup gets without opting in to more
+    // two buffers of the ten moving populations (80 B per cell, nz rounded up
+    // to a multiple of 64) and the reduction buffer must fit the 64 KB of LDS
+    // a workgroup gets without opting in to more
     if (ncols < 1 || nz < 3 || nz > 704 || !bytes) return set_error(LBM_E_INVAL, "need ncols >= 1 and 3 <= nz <= 704");
     *bytes = gplan(ncols, nz).total;
     return LBM_OK;
@@ -320,6 +414,7 @@ lbm_status gray_init(int32_t ncols, int32_t nz, int32_t walls, const double* eps
     const double* lw = lid ? lid : zero;
     for (int k = 0; k < Q; ++k)
         a.wterm[k] = (float)(6.0 * weight(k) * rho0 * (D3Q19::ex[k] * lw[0] + D3Q19::ey[k] * lw[1] + D3Q19::ez[k] * lw[2]));
+    a.lid = (lw[0] != 0.0 || lw[1] != 0.0 || lw[2] != 0.0) ? 1 : 0;
     s = upload_cells(c, eps, nu_eff, drag);
     if (s == LBM_OK) s = gray_reset(c);
     if (s != LBM_OK) { delete c; return s; }
