@@ -122,9 +122,10 @@ def run_bed(s: Setup, porosity, seed):
     sec = time.perf_counter() - t0
     u_sup, _, por = ctx.average_profile()
     K = ctx.permeability(z0=s.bed_top // 4, z1=3 * s.bed_top // 4)
+    layout = ctx.params.layout
     del ctx
     return {"porosity": porosity, "seed": seed, "eps_bed": eps_bed, "eps": por, "u": u_sup, "steps": steps,
-            "seconds": sec, "K_bed": K, "cells": s.nx * s.ny * s.nz}
+            "seconds": sec, "K_bed": K, "cells": s.nx * s.ny * s.nz, "layout": layout}
 
 
 def run_revs(s: Setup):
@@ -257,7 +258,7 @@ def evaluate(net: mlp.ClosureNet, bed, s: Setup, C_kc):
     """Learned closure and the reference models on one bed."""
     nu, G, eps = s.nu, s.force, bed["eps"]
     res = {"porosity": bed["porosity"], "seed": bed["seed"], "pore_scale_seconds": bed["seconds"],
-           "pore_scale_steps": bed["steps"]}
+           "pore_scale_steps": bed["steps"], "pore_scale_layout": bed["layout"]}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nue, drag = net.closure(eps, nu)
@@ -291,7 +292,8 @@ def experiment(s: Setup, init_seed=0):
     beds = []
     for e, seed in s.train + s.test:
         b = run_bed(s, e, seed)
-        log(f"bed eps {e} seed {seed}: bed porosity {b['eps_bed']:.4f}, {b['steps']} steps, {b['seconds']:.2f} s")
+        log(f"bed eps {e} seed {seed}: bed porosity {b['eps_bed']:.4f}, {b['steps']} steps, {b['seconds']:.2f} s "
+            f"({b['layout']} layout)")
         beds.append(b)
     train_beds, test_beds = beds[:len(s.train)], beds[len(s.train):]
     nu, G = s.nu, s.force
