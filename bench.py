@@ -305,6 +305,38 @@ def rev_cpu_baseline(doms, params, budget_s=15.0):
             "sample": f"one 48^3 REV cube of the batch ({d.name}), {nsteps} steps, FP64 two-grid, {dt:.1f} s"}
 
 
+def copy_ceiling(args):
+    """Plain device-to-device copies (one read and one write stream) from
+    64 MiB to 8 GiB each way, timed with HIP events: a working set inside
+    the 256 MB last-level cache shows the fabric's rate, larger ones the
+    streaming rate HBM sustains for buffers of the sweep's size."""
+    import torch
+
+    torch.cuda.set_device(0)
+    rows = []
+    for mib in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        n = mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        reps = max(10, int(40 * 1024 / mib))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tbs = 2 * mib * (1 << 20) / (ms * 1e-3) / 1e12
+        log(f"copy {mib} MiB each way: {ms:.4f} ms, {tbs:.2f} TB/s read + write")
+        rows.append({"mib_each_way": mib, "ms": round(ms, 5), "tb_per_s": round(tbs, 3)})
+        del a, b
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "device copy, one read and one write stream", "copies": rows}), flush=True)
+
+
 def weak_block(args):
     """The paper's weak-scaling block shape on one GPU (Sec. 3, the MLUPS-per-
     core figure: one 151^3 block with one sphere of diameter 90 per core, TRT):
@@ -445,10 +477,12 @@ def main():
                          "rev-batch BLOCK,WORKGROUPS_PER_SAMPLE")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 2 GiB device copy (reference for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("bed", "rev-batch", "closure-kernels", "weak-block"), default="bed",
+    ap.add_argument("--workload", choices=("bed", "rev-batch", "closure-kernels", "weak-block", "copy-ceiling"),
+                    default="bed",
                     help="bed: the large coupled domain (default); rev-batch: the batched REV cubes; "
                          "closure-kernels: closure network and gray column speed; weak-block: the paper's "
-                         "weak-scaling block shape, SBB against CLI")
+                         "weak-scaling block shape, SBB against CLI; copy-ceiling: device-copy rate against "
+                         "buffer size (the practical streaming ceiling)")
     ap.add_argument("--samples", type=int, default=512, help="rev-batch: number of cubes")
     ap.add_argument("--chunk", type=int, default=2000, help="rev-batch: steps per persistent launch")
     ap.add_argument("--max-steps", type=int, default=2_000_000, help="rev-batch: cap per sample")
@@ -471,6 +505,9 @@ def main():
         return
     if args.workload == "weak-block":
         weak_block(args)
+        return
+    if args.workload == "copy-ceiling":
+        copy_ceiling(args)
         return
 
     import numpy as np

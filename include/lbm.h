@@ -223,14 +223,21 @@ lbm_status lbm_steps_done(lbm_ctx* ctx, int64_t* steps);
  * (64, 128, 256, 512 or 1024; the brick layout runs one brick of 64 cells
  * per wavefront) and flags: LBM_LAUNCH_XCD_REMAP deals
  * consecutive tiles to one XCD instead of round-robin, LBM_LAUNCH_NONTEMPORAL
- * marks the aligned population streams non-temporal.  Every configuration
- * gives bit-identical results.  lbm_autotune times every configuration for
- * steps_per_trial steps on the context itself, keeps the fastest and restores
- * the state (host copy, or the rest state if no step was taken); the choice
- * is cached per process by (architecture, shape, layout, bc) and reused by
- * later lbm_init calls.  Synchronises. */
+ * marks the aligned population streams non-temporal, LBM_LAUNCH_CELLS_2 /
+ * LBM_LAUNCH_CELLS_4 (not both; brick layout only, LBM_E_INVAL otherwise)
+ * make each thread update 2 or 4 cells in turn (each workgroup steps that
+ * many groups of bricks, group b, b + G, ... for a grid of G workgroups;
+ * default one cell per thread).  Every configuration gives bit-identical
+ * results.  lbm_autotune times every workgroup size with every combination
+ * of the first two flags for steps_per_trial steps on the context itself,
+ * then (brick layout) 2 and 4 cells per thread at the best of those, keeps the
+ * fastest and restores the state (host copy, or the rest state if no step was
+ * taken); the choice is cached per process by (architecture, shape, layout,
+ * bc) and reused by later lbm_init calls.  Synchronises. */
 #define LBM_LAUNCH_XCD_REMAP 1
 #define LBM_LAUNCH_NONTEMPORAL 2
+#define LBM_LAUNCH_CELLS_2 4
+#define LBM_LAUNCH_CELLS_4 8
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t flags);
 lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t* block, int32_t* flags);
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t steps_per_trial);
@@ -260,10 +267,13 @@ lbm_status lbm_autotune_layout(const lbm_geometry* g, const lbm_params* params, 
  * resident, and teams of workgroups_per_domain pop domains from a
  * largest-first queue.  Brick layout (all domains in one brick array, one
  * brick-sweep launch per step): workgroup size 64..1024 (one brick per
- * wavefront); workgroups_per_domain is validated (1..64) and otherwise
- * unused.  Results are bit-identical for every shape.  lbm_autotune on a
- * batched context (before any step) times the shapes on steps_per_trial
- * steps of all domains, keeps the fastest and restores the rest state. */
+ * wavefront), and the second value is the cells per thread instead (1, 2
+ * or 4: each workgroup steps that many groups of bricks in turn).  Results
+ * are bit-identical for every shape.  lbm_autotune on a batched context
+ * (before any step) times the shapes on steps_per_trial steps of all
+ * domains (brick layout: sizes and hints at one cell per thread, then 2 and
+ * 4 cells per thread at the best), keeps the fastest and restores the rest
+ * state. */
 lbm_status lbm_batch_set_launch(lbm_ctx* ctx, int32_t block, int32_t workgroups_per_domain);
 lbm_status lbm_batch_get_launch(lbm_ctx* ctx, int32_t* block, int32_t* workgroups_per_domain);
 

@@ -54,7 +54,7 @@ struct TuneKey {
     }
 };
 std::mutex g_mu;
-std::map<TuneKey, std::pair<int, int>> g_cache;
+std::map<TuneKey, std::pair<int, int>> g_cache;  // block, nt | W << 1
 
 #define HIPCHK(expr, what)                                                                                  \
     do {                                                                                                    \
@@ -80,7 +80,7 @@ struct BrickBatch {
     std::vector<int64_t> steps;
     std::vector<int32_t> status;
     std::vector<double> uprev;
-    int block = 1024, nt = 1, W = 1;
+    int block = 1024, nt = 1, W = 1;  // W: cells per thread of the brick sweep (1, 2 or 4)
     std::string arch;
 };
 
@@ -224,6 +224,7 @@ lbm_status sweep_step(BrickBatch* b, const Lists& L, int64_t shift, bool check) 
         a.k = b->k;
         a.xcd_remap = 0;
         a.nt = b->nt;
+        a.cpt = b->W;
         HIPCHK(launch_sweep_bricks(a, b->bc, b->block, check, b->stream), "brick batch sweep");
     }
     return LBM_OK;
@@ -347,7 +348,11 @@ lbm_status bbatch_init(const std::vector<DomainGeo>& doms, const lbm_params& p, 
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_cache.find({b->arch, b->ndom, b->nb});
-        if (it != g_cache.end()) { b->block = it->second.first; b->nt = it->second.second; }
+        if (it != g_cache.end()) {
+            b->block = it->second.first;
+            b->nt = it->second.second & 1;
+            b->W = it->second.second >> 1;
+        }
     }
     st = reset(b);
     if (st != LBM_OK) { delete b; return st; }
@@ -567,41 +572,50 @@ lbm_status bbatch_autotune(BrickBatch* b, int32_t steps_per_trial) {
     HIPCHK(hipEventCreate(&e0), "event");
     HIPCHK(hipEventCreate(&e1), "event");
     float best = 1e30f;
-    int bb = b->block, bn = b->nt;
+    int bb = b->block, bn = b->nt, bw = b->W;
     lbm_status s = LBM_OK;
+    auto trial = [&](int block, int nt, int W) {
+        b->block = block;
+        b->nt = nt;
+        b->W = W;
+        s = reset(b);
+        if (s != LBM_OK) return;
+        (void)hipEventRecord(e0, b->stream);
+        s = bbatch_step(b, steps_per_trial);
+        (void)hipEventRecord(e1, b->stream);
+        (void)hipEventSynchronize(e1);
+        if (s != LBM_OK) return;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bb = block; bn = nt; bw = W; }
+    };
+    // workgroup size and hints at one cell per thread, then cells per
+    // thread at the best of those
     for (int block : {256, 512, 1024})
-        for (int nt = 0; nt < 2 && s == LBM_OK; ++nt) {
-            b->block = block;
-            b->nt = nt;
-            s = reset(b);
-            if (s != LBM_OK) break;
-            (void)hipEventRecord(e0, b->stream);
-            s = bbatch_step(b, steps_per_trial);
-            (void)hipEventRecord(e1, b->stream);
-            (void)hipEventSynchronize(e1);
-            if (s != LBM_OK) break;
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) { best = ms; bb = block; bn = nt; }
-        }
+        for (int nt = 0; nt < 2 && s == LBM_OK; ++nt) trial(block, nt, 1);
+    const int b1 = bb, n1 = bn;
+    for (int W : {2, 4})
+        if (s == LBM_OK) trial(b1, n1, W);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->block = bb;
     b->nt = bn;
+    b->W = bw;
     lbm_status s2 = reset(b);
     if (s != LBM_OK) return s;
     if (s2 != LBM_OK) return s2;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[{b->arch, b->ndom, b->nb}] = {bb, bn};
+    g_cache[{b->arch, b->ndom, b->nb}] = {bb, bn | (bw << 1)};
     return LBM_OK;
 }
 
 // block: threads per workgroup of the brick sweep (one brick per wavefront);
-// W (workgroups per domain) has no meaning here and is only validated
+// W: cells per thread, i.e. groups of block / 64 bricks each workgroup steps
+// in turn (1, 2 or 4)
 lbm_status bbatch_set_launch(BrickBatch* b, int32_t block, int32_t W) {
     if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
         return set_error(LBM_E_INVAL, "block must be 64, 128, 256, 512 or 1024");
-    if (W < 1 || W > 64) return set_error(LBM_E_INVAL, "workgroups per domain must be in [1, 64]");
+    if (W != 1 && W != 2 && W != 4) return set_error(LBM_E_INVAL, "brick batches take 1, 2 or 4 cells per thread");
     b->block = block;
     b->W = W;
     return LBM_OK;

@@ -171,6 +171,7 @@ struct lbm_ctx {
     int block = 256;
     int xcd_remap = 1;
     int nt = 0;
+    int cpt = 1;  // cells per thread: tiles each workgroup steps in turn
     SweepArgs sa{};
     int64_t n_fluid = 0;
     std::string arch;
@@ -179,6 +180,19 @@ struct lbm_ctx {
 };
 
 namespace {
+
+// launch flags (LBM_LAUNCH_*) <-> context fields; flags are validated by
+// the caller
+void set_flags(lbm_ctx* c, int flags) {
+    c->xcd_remap = (flags & LBM_LAUNCH_XCD_REMAP) ? 1 : 0;
+    c->nt = (flags & LBM_LAUNCH_NONTEMPORAL) ? 1 : 0;
+    c->cpt = (flags & LBM_LAUNCH_CELLS_4) ? 4 : ((flags & LBM_LAUNCH_CELLS_2) ? 2 : 1);
+}
+
+int get_flags(const lbm_ctx* c) {
+    return (c->xcd_remap ? LBM_LAUNCH_XCD_REMAP : 0) | (c->nt ? LBM_LAUNCH_NONTEMPORAL : 0) |
+           (c->cpt == 2 ? LBM_LAUNCH_CELLS_2 : 0) | (c->cpt == 4 ? LBM_LAUNCH_CELLS_4 : 0);
+}
 
 MomentArgs moment_args(const lbm_ctx* c) {
     MomentArgs m{};
@@ -277,6 +291,7 @@ lbm_status step_single(lbm_ctx* c, int64_t n) {
         a.pvb = a.B ? a.B + Q * c->P.stride : a.pva;
         a.xcd_remap = c->xcd_remap;
         a.nt = c->nt;
+        a.cpt = c->cpt;
         hipError_t e = launch_sweep(a, c->p.layout, par, c->d.bc, c->block, c->stream);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
         if (c->p.layout != LBM_LAYOUT_AA) c->cur = 1 - c->cur;
@@ -470,8 +485,7 @@ lbm_status lbm_init(const lbm_geometry* g, const lbm_params* p, void* dev_buf, i
         auto it = g_tune_cache.find({c->arch, nx, ny, nz, p->layout, G.desc.bc});
         if (it != g_tune_cache.end()) {
             c->block = it->second.first;
-            c->xcd_remap = it->second.second & 1;
-            c->nt = (it->second.second >> 1) & 1;
+            set_flags(c, it->second.second);
         }
     }
     hipError_t e = hipSuccess;
@@ -686,17 +700,21 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t flags) {
     if (!c || c->batch) return fail(LBM_E_INVAL, "launch shape applies to single-domain contexts");
     if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
         return fail(LBM_E_INVAL, "block must be 64, 128, 256, 512 or 1024");
-    if (flags & ~(LBM_LAUNCH_XCD_REMAP | LBM_LAUNCH_NONTEMPORAL)) return fail(LBM_E_INVAL, "unknown launch flags");
+    if (flags & ~(LBM_LAUNCH_XCD_REMAP | LBM_LAUNCH_NONTEMPORAL | LBM_LAUNCH_CELLS_2 | LBM_LAUNCH_CELLS_4))
+        return fail(LBM_E_INVAL, "unknown launch flags");
+    if ((flags & LBM_LAUNCH_CELLS_2) && (flags & LBM_LAUNCH_CELLS_4))
+        return fail(LBM_E_INVAL, "LBM_LAUNCH_CELLS_2 and LBM_LAUNCH_CELLS_4 exclude each other");
+    if ((flags & (LBM_LAUNCH_CELLS_2 | LBM_LAUNCH_CELLS_4)) && c->p.layout != LBM_LAYOUT_BRICK)
+        return fail(LBM_E_INVAL, "more than one cell per thread needs the brick layout");
     c->block = block;
-    c->xcd_remap = (flags & LBM_LAUNCH_XCD_REMAP) ? 1 : 0;
-    c->nt = (flags & LBM_LAUNCH_NONTEMPORAL) ? 1 : 0;
+    set_flags(c, flags);
     return LBM_OK;
 }
 
 lbm_status lbm_get_launch(lbm_ctx* c, int32_t* block, int32_t* flags) {
     if (!c || c->batch) return fail(LBM_E_INVAL, "launch shape applies to single-domain contexts");
     if (block) *block = c->block;
-    if (flags) *flags = (c->xcd_remap ? LBM_LAUNCH_XCD_REMAP : 0) | (c->nt ? LBM_LAUNCH_NONTEMPORAL : 0);
+    if (flags) *flags = get_flags(c);
     return LBM_OK;
 }
 
@@ -724,28 +742,33 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial) {
     HIP_TRY(hipEventCreate(&e0), "event");
     HIP_TRY(hipEventCreate(&e1), "event");
     float best = 1e30f;
-    int bb = c->block, br = c->xcd_remap, bn = c->nt;
+    int bb = c->block, bf = get_flags(c);
+    auto trial = [&](int blk, int fl) {
+        c->block = blk;
+        set_flags(c, fl);
+        s = step_single(c, 2);  // warm-up (even + odd for AA)
+        if (s != LBM_OK) return;
+        hipEventRecord(e0, c->stream);
+        s = step_single(c, steps_per_trial);
+        if (s != LBM_OK) return;
+        hipEventRecord(e1, c->stream);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bb = blk; bf = fl; }
+    };
+    // workgroup size, XCD remap and hints at one cell per thread, then (brick
+    // layout) two and four cells per thread at the best of those
     for (int blk : blocks)
-        for (int fl = 0; fl < 4 && s == LBM_OK; ++fl) {
-            c->block = blk;
-            c->xcd_remap = fl & 1;
-            c->nt = (fl >> 1) & 1;
-            s = step_single(c, 2);  // warm-up (even + odd for AA)
-            if (s != LBM_OK) break;
-            hipEventRecord(e0, c->stream);
-            s = step_single(c, steps_per_trial);
-            if (s != LBM_OK) break;
-            hipEventRecord(e1, c->stream);
-            hipEventSynchronize(e1);
-            float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best) { best = ms; bb = blk; br = c->xcd_remap; bn = c->nt; }
-        }
+        for (int fl = 0; fl < 4 && s == LBM_OK; ++fl) trial(blk, fl);
+    const int b1 = bb, f1 = bf;
+    if (c->p.layout == LBM_LAYOUT_BRICK)
+        for (int cells : {LBM_LAUNCH_CELLS_2, LBM_LAUNCH_CELLS_4})
+            if (s == LBM_OK) trial(b1, f1 | cells);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     c->block = bb;
-    c->xcd_remap = br;
-    c->nt = bn;
+    set_flags(c, bf);
     lbm_status s2 = LBM_OK;
     if (at_rest) {
         hipError_t e = reset_state(c);
@@ -757,7 +780,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t steps_per_trial) {
     if (s != LBM_OK) return s;
     if (s2 != LBM_OK) return s2;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[{c->arch, c->d.nx, c->d.ny, c->d.nz, c->p.layout, c->d.bc}] = {bb, br | (bn << 1)};
+    g_tune_cache[{c->arch, c->d.nx, c->d.ny, c->d.nz, c->p.layout, c->d.bc}] = {bb, bf};
     return LBM_OK;
 }
 

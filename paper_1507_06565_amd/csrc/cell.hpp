@@ -136,6 +136,15 @@ struct PopBases {
         return (__attribute__((address_space(1))) char*)p[k] + (idx << 2);
     }
 };
+// PopWide: one base and the distance between arrays in bytes (64-bit); the
+// array base is formed in scalar registers where it is used, so a loop over
+// several bricks keeps two values live instead of 19 pointers.
+struct PopWide {
+    uint64_t base, sbytes;
+    __device__ __forceinline__ __attribute__((address_space(1))) char* at(int k, uint32_t idx) const {
+        return (__attribute__((address_space(1))) char*)(base + (uint64_t)k * sbytes) + (idx << 2);
+    }
+};
 struct PopStrided {
     float* base;
     uint32_t stride;  // floats between consecutive arrays

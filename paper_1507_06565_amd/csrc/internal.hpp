@@ -93,6 +93,7 @@ struct SweepArgs {
     CellConsts k;
     int32_t xcd_remap;
     int32_t nt;           // non-temporal hints on the aligned streams
+    int32_t cpt;          // cells per thread: tiles (brick groups) each workgroup steps in turn, 1, 2 or 4
 };
 
 // Brick layout (4x4x4 bricks, bricks without fluid cells not stored): map

@@ -201,7 +201,8 @@ class Context:
 
     # --- launch configuration
     def set_launch(self, block, flags=1):
-        """flags: 1 = XCD-contiguous tiles, 2 = non-temporal aligned streams."""
+        """flags (lbm_set_launch): 1 = XCD-contiguous tiles, 2 = non-temporal
+        aligned streams, 4 / 8 = two / four cells per thread."""
         check(lib.lbm_set_launch(self.ptr, block, flags), "lbm_set_launch")
 
     def get_launch(self):
@@ -210,6 +211,8 @@ class Context:
         return b.value, r.value
 
     def batch_set_launch(self, block, workgroups_per_domain):
+        """AA batches: workgroups stepping one domain together (1..64); brick
+        batches: cells per thread (1, 2 or 4)."""
         check(lib.lbm_batch_set_launch(self.ptr, block, workgroups_per_domain), "lbm_batch_set_launch")
 
     def batch_get_launch(self):

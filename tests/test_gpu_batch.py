@@ -88,7 +88,10 @@ def test_batch_launch_shapes_bitwise(layout):
     lbm = _lbm()
     doms = batch_domains()
     base = None
-    for block, w in [(256, 1), (512, 2), (1024, 4), (256, 3), (512, 16)]:
+    # AA: workgroups per domain; brick: cells per thread
+    shapes = [(256, 1), (512, 2), (1024, 4), (256, 3), (512, 16)] if layout == "aa" else \
+        [(256, 1), (512, 2), (1024, 4), (64, 4), (128, 2)]
+    for block, w in shapes:
         ctx = lbm.Context(lbm.Geometry(doms), params(layout))
         ctx.batch_set_launch(block, w)
         steps = ctx.run_to_steady(rel_tol=1e-6, check_every=50, max_steps=3000)

@@ -106,8 +106,9 @@ def test_brick_launch_shapes_bitwise():
     a = ctx_for(d, P, "twogrid")
     a.step(41)
     base = a.fields()[1]
+    # flags: XCD remap 1, non-temporal 2, two / four cells per thread 4 / 8
     for block in (64, 128, 256, 512, 1024):
-        for flags in (0, 1, 2, 3):
+        for flags in (0, 1, 2, 3, 4, 8, 4 | 2, 8 | 1):
             b = ctx_for(d, P, "brick", block, flags)
             b.step(41)
             assert np.array_equal(b.fields()[1], base), (block, flags)

@@ -158,6 +158,10 @@ def test_launch_shapes_bitwise():
                 if base is None:
                     base = u
                 assert np.array_equal(u, base), (layout, block, flags)
+    # more than one cell per thread (flags 4 and 8) is a brick-layout shape
+    for layout in ("aa", "twogrid"):
+        with pytest.raises(RuntimeError):
+            gpu_run(d, p, 1, layout, 256, 4)
 
 
 def test_all_solid_domain():
