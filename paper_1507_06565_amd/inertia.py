@@ -143,9 +143,7 @@ def gray_steady_forchheimer(eps, nue, drag, phi, G, s: CL.Setup):
 
     from . import gray
 
-    e = np.array(eps, dtype=np.float64)
-    e[0] = e[-1] = 1.0
-    e = np.clip(e, 1e-3, 1.0)
+    e, nue, drag = CL.wall_free_fluid(eps, nue, drag, s.nu)
     ph = np.array(phi, dtype=np.float64)
     ph[0] = ph[-1] = 0.0
     col = gray.GrayColumns(e, nue, drag, G=(G, 0.0, 0.0), walls=True)
