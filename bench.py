@@ -82,10 +82,34 @@ def sampled_window_check(dom, params, ctx_factory, geo, nsteps=20, nwin=16, seed
     return (num / den) ** 0.5 if den > 0 else float("nan")
 
 
-def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0):
+def host_cpu():
+    """Model name of the host CPU (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of this thread's later parallel regions
+    (the oracle's); returns False if no OpenMP runtime is loaded."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0, single_s=4.0):
     """The FP64 oracle, as it is, on a slab of the workload straddling the
     bed surface; after one untimed step (threads and pages warm up), two
-    timed steps calibrate the step count to about budget_s."""
+    timed steps calibrate the step count to about budget_s.  Then the same
+    on one thread for about single_s (the single-core rate)."""
     import oracle
 
     sim = oracle.Sim(dom, params, window=((0, 0, z0), (dom.nx, dom.ny, nz_win)), geometry=geo_oracle)
@@ -99,9 +123,20 @@ def cpu_baseline(dom, params, geo_oracle, z0, nz_win, budget_s=15.0):
     dt = time.perf_counter() - t
     cells = dom.nx * dom.ny * nz_win
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    single = None
+    if _omp_threads(1):
+        t = time.perf_counter()
+        sim.step(1)
+        t1s = time.perf_counter() - t
+        n1 = int(max(1, min(50, single_s / max(t1s, 1e-3))))
+        t = time.perf_counter()
+        sim.step(n1)
+        single = round(cells * n1 / (time.perf_counter() - t) / 1e6, 2)
+        _omp_threads(threads)
     return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{dom.nx}x{dom.ny}x{nz_win} slab (z {z0}..{z0 + nz_win - 1}) of the workload, "
-                      f"{nsteps} steps, FP64 two-grid, {dt:.1f} s"}
+                      f"{nsteps} steps, FP64 two-grid, {dt:.1f} s",
+            "single_core_mlups": single, "cpu": host_cpu()}
 
 
 def gpu_runtime_loaded():
@@ -302,7 +337,8 @@ def rev_cpu_baseline(doms, params, budget_s=15.0):
     dt = time.perf_counter() - t
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": d.nx ** 3 * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"one 48^3 REV cube of the batch ({d.name}), {nsteps} steps, FP64 two-grid, {dt:.1f} s"}
+            "sample": f"one 48^3 REV cube of the batch ({d.name}), {nsteps} steps, FP64 two-grid, {dt:.1f} s",
+            "cpu": host_cpu()}
 
 
 def copy_ceiling(args):
