@@ -342,13 +342,26 @@ def rev_cpu_baseline(doms, params, budget_s=15.0):
 
 
 def copy_ceiling(args):
-    """Plain device-to-device copies (one read and one write stream) from
-    64 MiB to 8 GiB each way, timed with HIP events: a working set inside
-    the 256 MB last-level cache shows the fabric's rate, larger ones the
-    streaming rate HBM sustains for buffers of the sweep's size."""
+    """The streaming ceiling for the sweep's working set.  (1) lbm_stream_probe:
+    exactly the population bytes of the large bed's brick sweep (1,778,143
+    bricks x 19 x 64 FP32, read once and written once, 17.3 GB), in the
+    sweep's layout and grouped per brick, with nothing else.  (2) Plain
+    torch device copies from 64 MiB to 8 GiB per buffer: a working set inside
+    the 256 MB last-level cache shows the fabric's rate, larger ones HBM."""
     import torch
 
+    from paper_1507_06565_amd import lbm
+
     torch.cuda.set_device(0)
+    nb = 1778143
+    probe = {}
+    for grouped in (False, True):
+        ms = lbm.stream_probe(nb, grouped=grouped, passes=20)
+        tbs = 2 * nb * 64 * 19 * 4 / (ms * 1e-3) / 1e12
+        name = "grouped" if grouped else "sweep_layout"
+        log(f"stream probe ({name}): {nb} bricks, {ms:.4f} ms per pass, {tbs:.2f} TB/s read + write")
+        probe[name] = {"ms": round(ms, 4), "tb_per_s": round(tbs, 3)}
+        torch.cuda.empty_cache()
     rows = []
     for mib in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
         n = mib * (1 << 20) // 4
@@ -370,7 +383,8 @@ def copy_ceiling(args):
         rows.append({"mib_each_way": mib, "ms": round(ms, 5), "tb_per_s": round(tbs, 3)})
         del a, b
         torch.cuda.empty_cache()
-    print(json.dumps({"workload": "device copy, one read and one write stream", "copies": rows}), flush=True)
+    print(json.dumps({"workload": "streaming ceiling", "stream_probe_bricks": nb, "stream_probe": probe,
+                      "torch_copies": rows}), flush=True)
 
 
 def weak_block(args):

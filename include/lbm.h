@@ -261,6 +261,19 @@ lbm_status lbm_autotune_layout_bytes(const lbm_geometry* g, const lbm_params* pa
 lbm_status lbm_autotune_layout(const lbm_geometry* g, const lbm_params* params, void* dev_buf, int64_t bytes,
                                void* hip_stream, int32_t steps_per_trial, int32_t* layout, double* ms_per_step);
 
+/* Streaming ceiling of the brick sweep's access pattern (a measurement aid,
+ * not a step of the method): copies nbricks x 64 cells x 19 FP32 values from
+ * src to dst with one wavefront per brick and non-temporal stores, exactly
+ * the population bytes a sweep of that many bricks reads and writes once,
+ * with nothing else.  grouped = 0: the sweep's layout (population k of brick
+ * b at element k*64*nbricks + 64*b + lane); grouped = 1: a brick's 19
+ * populations contiguous ((19*b + k)*64 + lane).  src and dst are
+ * caller-owned device buffers of at least 4864*nbricks bytes each (dst is
+ * overwritten); three untimed passes, then passes timed with HIP events on
+ * hip_stream; *ms_per_pass receives the average.  Synchronises. */
+lbm_status lbm_stream_probe(const void* src, void* dst, int64_t nbricks, int32_t grouped, int32_t passes,
+                            void* hip_stream, double* ms_per_pass);
+
 /* Launch shape of a batched context.  AA layout (one persistent kernel):
  * workgroup size (256, 512 or 1024) and workgroups that step one domain
  * together (1..64); the persistent launch holds as many workgroups as can be

@@ -14,7 +14,7 @@ OUT = os.path.join(PKG, "libmi355lbm.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["sweep.hip", "reduce.hip", "batch.hip", "gray.hip", "mlp.hip"]
+HIP_SOURCES = ["sweep.hip", "reduce.hip", "batch.hip", "gray.hip", "mlp.hip", "probe.hip"]
 HOST_SOURCES = ["geometry.cpp", "images.cpp", "capi.cpp", "brick_batch.cpp"]
 
 

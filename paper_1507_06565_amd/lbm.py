@@ -112,6 +112,20 @@ def autotune_layout(geo: Geometry, params, steps_per_trial=10, device="cuda", st
     return LAYOUT_NAME[lay.value], ms.value
 
 
+def stream_probe(nbricks, grouped=False, passes=20, device="cuda", stream=None):
+    """Milliseconds per pass of lbm_stream_probe: the brick sweep's population
+    bytes for nbricks bricks (19 x 64 FP32 per brick read and written once),
+    in the sweep's layout or grouped per brick; allocates the two buffers."""
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    n = int(nbricks) * 64 * 19
+    a = torch.zeros(n, dtype=torch.float32, device=s.device)
+    b = torch.empty_like(a)
+    ms = C.c_double()
+    check(lib.lbm_stream_probe(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), int(nbricks), int(bool(grouped)),
+                               int(passes), C.c_void_p(s.cuda_stream), C.byref(ms)), "lbm_stream_probe")
+    return ms.value
+
+
 class Context:
     """Owns an lbm_ctx* and the torch tensor that backs its device memory.
     params.layout == "auto" picks the layout with autotune_layout first."""
