@@ -62,7 +62,8 @@ lbm_status gray_set_cells(gray_ctx* ctx, const double* eps, const double* nu_eff
 lbm_status gray_set_forchheimer(gray_ctx* ctx, const double* phi);
 lbm_status gray_reset(gray_ctx* ctx);
 
-/* Advance every column exactly nsteps steps (one launch, LDS-resident). */
+/* Advance every column exactly nsteps steps (one launch; the state stays on
+ * chip, in registers and LDS, between the load and the store). */
 lbm_status gray_run(gray_ctx* ctx, int64_t nsteps);
 
 /* Advance every column until the FP64 sum of u_x over the column changes by
