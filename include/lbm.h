@@ -261,6 +261,26 @@ lbm_status lbm_autotune_layout_bytes(const lbm_geometry* g, const lbm_params* pa
 lbm_status lbm_autotune_layout(const lbm_geometry* g, const lbm_params* params, void* dev_buf, int64_t bytes,
                                void* hip_stream, int32_t steps_per_trial, int32_t* layout, double* ms_per_step);
 
+/* The autotuners' choices (lbm_autotune, lbm_autotune_layout and the batch
+ * autotuners) are cached per process; these two calls carry them to a later
+ * process.  Text, one entry per line, fields separated by spaces, lines
+ * starting with '#' ignored:
+ *   sweep ARCH NX NY NZ LAYOUT BC BLOCK FLAGS
+ *   layout ARCH DOMAINS NX NY NZ BC COLLISION CELLS LAYOUT MS_PER_STEP
+ *   brick-batch ARCH DOMAINS BRICKS BLOCK NONTEMPORAL CELLS_PER_THREAD
+ *   aa-batch ARCH DOMAINS CELLS BLOCK WORKGROUPS_PER_DOMAIN
+ * (ARCH is the device's architecture name; the other fields are integers
+ * with the meanings and ranges of lbm_set_launch, lbm_batch_set_launch and
+ * lbm_params, MS_PER_STEP a decimal number.)  lbm_tuning_export writes the
+ * text and its terminating NUL to buf when capacity exceeds its length, and
+ * the length without the NUL to *length in any case (buf may be NULL with
+ * capacity 0 to ask for the length).  lbm_tuning_import adds the entries of
+ * a NUL-terminated text to the caches, replacing entries with the same key;
+ * a line that is not a valid entry fails the whole call with LBM_E_INVAL
+ * (naming the line) and changes nothing.  Host only: no device call. */
+lbm_status lbm_tuning_export(char* buf, int64_t capacity, int64_t* length);
+lbm_status lbm_tuning_import(const char* text);
+
 /* Streaming ceiling of the brick sweep's access pattern (a measurement aid,
  * not a step of the method): copies nbricks x 64 cells x 19 FP32 values from
  * src to dst with one wavefront per brick and non-temporal stores, exactly

@@ -64,6 +64,8 @@ _sig = {
     "lbm_autotune_layout_bytes": ([vp, P(Params), P(i64)], i32),
     "lbm_autotune_layout": ([vp, P(Params), vp, i64, vp, i32, P(i32), P(f64)], i32),
     "lbm_stream_probe": ([vp, vp, i64, i32, i32, vp, P(f64)], i32),
+    "lbm_tuning_export": ([C.c_char_p, i64, P(i64)], i32),
+    "lbm_tuning_import": ([C.c_char_p], i32),
     "lbm_batch_set_launch": ([vp, i32, i32], i32),
     "lbm_batch_get_launch": ([vp, P(i32), P(i32)], i32),
     "lbm_destroy": ([vp], None),

@@ -734,4 +734,27 @@ void batch_destroy(BatchCtx* b) {
     delete b;
 }
 
+// "aa-batch ARCH DOMAINS CELLS BLOCK WORKGROUPS_PER_DOMAIN"
+void abatch_tuning_export(std::string& out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : g_cache)
+        out += "aa-batch " + kv.first.arch + " " + std::to_string(kv.first.ndom) + " " +
+               std::to_string(kv.first.cells) + " " + std::to_string(kv.second.first) + " " +
+               std::to_string(kv.second.second) + "\n";
+}
+
+int abatch_tuning_import(const std::vector<std::string>& f, bool apply) {
+    if (f.empty() || f[0] != "aa-batch") return 0;
+    int64_t nd = 0, cells = 0, block = 0, w = 0;
+    if (f.size() != 6 || f[1].empty() || !parse_i64(f[2], nd) || !parse_i64(f[3], cells) || !parse_i64(f[4], block) ||
+        !parse_i64(f[5], w))
+        return -1;
+    if (nd < 1 || cells < 1 || (block != 256 && block != 512 && block != 1024) || w < 1 || w > 64) return -1;
+    if (apply) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[{f[1], (int)nd, cells}] = {(int)block, (int)w};
+    }
+    return 1;
+}
+
 }  // namespace lbm

@@ -629,4 +629,28 @@ lbm_status bbatch_get_launch(BrickBatch* b, int32_t* block, int32_t* W) {
 
 void bbatch_destroy(BrickBatch* b) { delete b; }
 
+// "brick-batch ARCH DOMAINS BRICKS BLOCK NT CELLS_PER_THREAD"
+void bbatch_tuning_export(std::string& out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : g_cache)
+        out += "brick-batch " + kv.first.arch + " " + std::to_string(kv.first.ndom) + " " +
+               std::to_string(kv.first.bricks) + " " + std::to_string(kv.second.first) + " " +
+               std::to_string(kv.second.second & 1) + " " + std::to_string(kv.second.second >> 1) + "\n";
+}
+
+int bbatch_tuning_import(const std::vector<std::string>& f, bool apply) {
+    if (f.empty() || f[0] != "brick-batch") return 0;
+    int64_t nd = 0, nb = 0, block = 0, nt = 0, w = 0;
+    if (f.size() != 7 || f[1].empty() || !parse_i64(f[2], nd) || !parse_i64(f[3], nb) || !parse_i64(f[4], block) ||
+        !parse_i64(f[5], nt) || !parse_i64(f[6], w))
+        return -1;
+    const bool ok_block = block == 64 || block == 128 || block == 256 || block == 512 || block == 1024;
+    if (nd < 1 || nb < 0 || !ok_block || (nt != 0 && nt != 1) || (w != 1 && w != 2 && w != 4)) return -1;
+    if (apply) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[{f[1], (int)nd, nb}] = {(int)block, (int)(nt | (w << 1))};
+    }
+    return 1;
+}
+
 }  // namespace lbm

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -808,6 +809,123 @@ LayoutKey layout_key(const lbm_geometry* g, const lbm_params* p, const std::stri
 }
 
 }  // namespace
+
+namespace {
+
+// "sweep ARCH NX NY NZ LAYOUT BC BLOCK FLAGS" and
+// "layout ARCH DOMAINS NX NY NZ BC COLLISION CELLS LAYOUT MS_PER_STEP"
+void single_tuning_export(std::string& out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune_cache) {
+        const TuneKey& k = kv.first;
+        out += "sweep " + k.arch + " " + std::to_string(k.nx) + " " + std::to_string(k.ny) + " " + std::to_string(k.nz) +
+               " " + std::to_string(k.layout) + " " + std::to_string(k.bc) + " " + std::to_string(kv.second.first) + " " +
+               std::to_string(kv.second.second) + "\n";
+    }
+    for (const auto& kv : g_layout_cache) {
+        const LayoutKey& k = kv.first;
+        char ms[32];
+        std::snprintf(ms, sizeof ms, "%.17g", kv.second.second);
+        out += "layout " + k.arch + " " + std::to_string(k.ndom) + " " + std::to_string(k.nx) + " " +
+               std::to_string(k.ny) + " " + std::to_string(k.nz) + " " + std::to_string(k.bc) + " " +
+               std::to_string(k.collision) + " " + std::to_string(k.cells) + " " + std::to_string(kv.second.first) +
+               " " + ms + "\n";
+    }
+}
+
+int single_tuning_import(const std::vector<std::string>& f, bool apply) {
+    if (f.empty()) return 0;
+    if (f[0] == "sweep") {
+        int64_t v[7];
+        if (f.size() != 9 || f[1].empty()) return -1;
+        for (int i = 0; i < 7; ++i)
+            if (!parse_i64(f[2 + i], v[i])) return -1;
+        const int64_t nx = v[0], ny = v[1], nz = v[2], layout = v[3], bc = v[4], block = v[5], flags = v[6];
+        const bool ok_block = block == 64 || block == 128 || block == 256 || block == 512 || block == 1024;
+        const int64_t cells = LBM_LAUNCH_CELLS_2 | LBM_LAUNCH_CELLS_4;
+        if (nx < 1 || ny < 1 || nz < 1 || layout < 0 || layout > 2 || bc < 0 || bc > 2 || !ok_block ||
+            (flags & ~(LBM_LAUNCH_XCD_REMAP | LBM_LAUNCH_NONTEMPORAL | cells)) || (flags & cells) == cells ||
+            ((flags & cells) && layout != LBM_LAYOUT_BRICK))
+            return -1;
+        if (apply) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[{f[1], (int)nx, (int)ny, (int)nz, (int)layout, (int)bc}] = {(int)block, (int)flags};
+        }
+        return 1;
+    }
+    if (f[0] == "layout") {
+        int64_t v[8];
+        double ms = 0.0;
+        if (f.size() != 11 || f[1].empty()) return -1;
+        for (int i = 0; i < 8; ++i)
+            if (!parse_i64(f[2 + i], v[i])) return -1;
+        if (!parse_f64(f[10], ms)) return -1;
+        const int64_t nd = v[0], nx = v[1], ny = v[2], nz = v[3], bc = v[4], coll = v[5], cells = v[6], layout = v[7];
+        if (nd < 1 || nx < 1 || ny < 1 || nz < 1 || bc < 0 || bc > 2 || coll < 0 || coll > 1 || cells < 1 ||
+            layout < 0 || layout > 2 || ms < 0.0)
+            return -1;
+        if (apply) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_layout_cache[{f[1], (int)nd, (int)nx, (int)ny, (int)nz, (int)bc, (int)coll, cells}] = {(int)layout, ms};
+        }
+        return 1;
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_tuning_export(char* buf, int64_t capacity, int64_t* length) {
+    if (!length || capacity < 0 || (capacity > 0 && !buf)) return fail(LBM_E_INVAL, "bad arguments");
+    std::string out = "# mi355lbm tuning cache v1\n";
+    single_tuning_export(out);
+    bbatch_tuning_export(out);
+    abatch_tuning_export(out);
+    *length = (int64_t)out.size();
+    if (buf && capacity > (int64_t)out.size()) std::memcpy(buf, out.c_str(), out.size() + 1);
+    return LBM_OK;
+}
+
+lbm_status lbm_tuning_import(const char* text) {
+    if (!text) return fail(LBM_E_INVAL, "bad arguments");
+    std::vector<std::vector<std::string>> lines;
+    {
+        std::string cur;
+        std::vector<std::string> f;
+        for (const char* q = text;; ++q) {
+            const char ch = *q;
+            if (ch == ' ' || ch == '\t' || ch == '\n' || ch == '\r' || ch == '\0') {
+                if (!cur.empty()) f.push_back(cur);
+                cur.clear();
+                if (ch == '\n' || ch == '\0') {
+                    lines.push_back(f);
+                    f.clear();
+                }
+                if (ch == '\0') break;
+            } else {
+                cur += ch;
+            }
+        }
+    }
+    // check every line first, so that a malformed text changes nothing
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t i = 0; i < lines.size(); ++i) {
+            const auto& f = lines[i];
+            if (f.empty() || f[0][0] == '#') continue;
+            const bool apply = pass == 1;
+            int r = single_tuning_import(f, apply);
+            if (r == 0) r = bbatch_tuning_import(f, apply);
+            if (r == 0) r = abatch_tuning_import(f, apply);
+            if (r != 1) return fail(LBM_E_INVAL, "tuning text, line " + std::to_string(i + 1) + ": " +
+                                                     (r == 0 ? "unknown entry kind" : "malformed entry"));
+        }
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

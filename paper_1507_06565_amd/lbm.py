@@ -112,6 +112,30 @@ def autotune_layout(geo: Geometry, params, steps_per_trial=10, device="cuda", st
     return LAYOUT_NAME[lay.value], ms.value
 
 
+def tuning_export():
+    """The autotuners' cached choices as text (lbm_tuning_export)."""
+    n = C.c_int64()
+    check(lib.lbm_tuning_export(None, 0, C.byref(n)), "lbm_tuning_export")
+    buf = C.create_string_buffer(n.value + 1)
+    check(lib.lbm_tuning_export(buf, n.value + 1, C.byref(n)), "lbm_tuning_export")
+    return buf.value.decode()
+
+
+def tuning_import(text):
+    """Add cached choices from text written by tuning_export (lbm_tuning_import)."""
+    check(lib.lbm_tuning_import(text.encode()), "lbm_tuning_import")
+
+
+def save_tuning(path):
+    with open(path, "w") as f:
+        f.write(tuning_export())
+
+
+def load_tuning(path):
+    with open(path) as f:
+        tuning_import(f.read())
+
+
 def stream_probe(nbricks, grouped=False, passes=20, device="cuda", stream=None):
     """Milliseconds per pass of lbm_stream_probe: the brick sweep's population
     bytes for nbricks bricks (19 x 64 FP32 per brick read and written once),

@@ -34,6 +34,16 @@ def test_layout_autotuner_single_domain():
     assert name in ("twogrid", "aa", "brick") and ms > 0
     # cached: the same answer without a buffer
     assert lbm.autotune_layout(geo, p)[0] == name
+    # the caches travel as text: the layout choice and the tuned launch of
+    # every candidate are in the export, and importing it back changes nothing
+    text = lbm.tuning_export()
+    lay_id = {"twogrid": 0, "aa": 1, "brick": 2}[name]
+    assert any(l.startswith("layout ") and l.split()[3:6] == [str(dom.nx), str(dom.ny), str(dom.nz)]
+               and l.split()[9] == str(lay_id) for l in text.splitlines()), text
+    assert sum(l.startswith("sweep ") and l.split()[2:5] == [str(dom.nx), str(dom.ny), str(dom.nz)]
+               for l in text.splitlines()) >= 2, text
+    lbm.tuning_import(text)
+    assert lbm.tuning_export() == text
     # a context with layout "auto" runs the chosen layout; fields equal every fixed layout's
     out = {}
     for lay in ("auto", "twogrid", "aa", "brick"):

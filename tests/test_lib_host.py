@@ -193,3 +193,34 @@ def test_link_count_limit(monkeypatch):
     monkeypatch.setenv("MI355LBM_MAX_LINKS", str(nlb - 1))
     with pytest.raises(lbm.LbmError, match="too many boundary links"):
         lbm.required_bytes(gb, p)
+
+
+def test_tuning_cache_round_trip():
+    """lbm_tuning_export / lbm_tuning_import carry every autotuner's cached
+    choices to another process as text: entries of all four kinds come back
+    out exactly; a malformed or unknown line fails the whole import, names
+    the line, and changes nothing."""
+    from paper_1507_06565_amd import lbm
+    entries = [
+        "sweep test-arch-a 512 256 1024 2 1 1024 2",
+        "sweep test-arch-a 128 64 256 1 2 256 1",
+        "layout test-arch-a 1 128 64 256 1 1 2097152 1 0.0562",
+        "brick-batch test-arch-a 512 2437120 512 1 1",
+        "aa-batch test-arch-a 48 8093696 512 4",
+    ]
+    lbm.tuning_import("# saved\n" + "\n".join(entries) + "\n")
+    out = lbm.tuning_export()
+    lines = set(out.splitlines())
+    for e in entries:
+        assert e in lines, e
+    lbm.tuning_import(out)  # its own export imports cleanly and changes nothing
+    assert lbm.tuning_export() == out
+    for bad, why in [("sweep test-arch-b 64 64 64 2 1 100 0", "malformed"),      # block 100
+                     ("sweep test-arch-b 64 64 64 0 1 256 4", "malformed"),      # cells per thread on a dense layout
+                     ("brick-batch test-arch-b 1 10 256 0 3", "malformed"),      # 3 cells per thread
+                     ("layout test-arch-b 1 8 8 8 1 1 512 2", "malformed"),      # missing time
+                     ("autotune test-arch-b 1 2 3", "unknown")]:
+        text = "sweep test-arch-b 32 32 32 0 0 128 0\n" + bad + "\n"
+        with pytest.raises(lbm.LbmError, match=f"line 2: {why}"):
+            lbm.tuning_import(text)
+        assert "test-arch-b" not in lbm.tuning_export()
