@@ -656,7 +656,10 @@ def main():
     if not args.no_closure:
         del ctx
         torch.cuda.empty_cache()
-        closure = closure_half()
+        try:
+            closure = closure_half()
+        except Exception as e:  # the sweep's line is still printed, with the failure named
+            closure = {"error": f"{type(e).__name__}: {e}"}
         log("closure:", closure)
 
     out = {
