@@ -118,3 +118,26 @@ def test_forchheimer_zero_is_the_stokes_model_bitwise():
     u0, g0 = oracle.gray_run(nz, eps, NU / eps, drag, G=(G, 0, 0), nsteps=300)
     u1, g1 = oracle.gray_run(nz, eps, NU / eps, drag, G=(G, 0, 0), nsteps=300, forch=np.zeros(nz))
     assert np.array_equal(u0, u1) and np.array_equal(g0, g1)
+
+
+@pytest.mark.parametrize("s", [0.5, 4.0])
+def test_steady_state_is_parametrised_by_lambda(s):
+    """TRT at fixed Lambda: the steady state of the Stokes-Brinkman column is
+    parametrised by Lambda alone, so scaling nu_eff, the drag and the force
+    by one factor s leaves the steady velocity unchanged (the continuum
+    balance nu_eff u'' - D u + eps G = 0 is homogeneous in the three); the
+    number of steps to reach it scales as 1/s.  Checked on a walled column
+    with a smoothed porosity step, where every term of the forcing and of the
+    implicit velocity is active."""
+    from paper_1507_06565_amd import workloads as W
+    nz, G = 66, 1e-6
+    eps, _, _ = W.smoothed_step_porosity(nz, 5)
+    eps = eps.copy()
+    eps[0] = eps[-1] = 1.0
+    K = 2.0 * eps ** 3 / (1 - eps + 1e-12) ** 2
+    nue = NU / eps
+    drag = np.where(eps < 1.0, eps * NU / K, 0.0)
+    u1, n1 = oracle.gray_to_steady(nz, eps, nue, drag, G=(G, 0, 0), walls=True, rel_tol=1e-13, check=200)
+    us, ns = oracle.gray_to_steady(nz, eps, s * nue, s * drag, G=(s * G, 0, 0), walls=True, rel_tol=1e-13, check=200)
+    assert np.max(np.abs(us[:, 0] - u1[:, 0])) <= 1e-9 * np.max(np.abs(u1[:, 0]))
+    assert abs(ns * s / n1 - 1.0) < 0.35, (n1, ns)
