@@ -33,6 +33,7 @@
 #include <numeric>
 
 #include "batch.hpp"
+#include "tuning.hpp"
 #include "cell.hpp"
 
 namespace lbm {

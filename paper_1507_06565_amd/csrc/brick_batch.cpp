@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "tuning.hpp"
 
 namespace lbm {
 

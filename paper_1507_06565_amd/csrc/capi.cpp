@@ -21,6 +21,7 @@
 
 #include "batch.hpp"
 #include "internal.hpp"
+#include "tuning.hpp"
 
 using namespace lbm;
 

@@ -3,9 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include <cmath>
 #include <cstdint>
-#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -31,30 +29,6 @@ lbm_status build_domain(const lbm_domain_desc& d, DomainGeo& out, std::string& e
 
 // error text for the calling thread (defined with the C ABI); returns s
 lbm_status set_error(lbm_status s, const std::string& msg);
-
-// Tuning caches as text, one entry per line, fields separated by spaces (the
-// entry kinds and their fields are listed in include/lbm.h).  export appends
-// this module's entries; import returns 1 for an entry of this module that
-// is valid (stored when apply is set), 0 for another module's kind, -1 for a
-// malformed entry of this module.
-inline bool parse_i64(const std::string& t, int64_t& v) {
-    if (t.empty()) return false;
-    char* end = nullptr;
-    const long long x = std::strtoll(t.c_str(), &end, 10);
-    if (*end != '\0') return false;
-    v = (int64_t)x;
-    return true;
-}
-inline bool parse_f64(const std::string& t, double& v) {
-    if (t.empty()) return false;
-    char* end = nullptr;
-    v = std::strtod(t.c_str(), &end);
-    return *end == '\0' && std::isfinite(v);
-}
-void bbatch_tuning_export(std::string& out);
-int bbatch_tuning_import(const std::vector<std::string>& f, bool apply);
-void abatch_tuning_export(std::string& out);
-int abatch_tuning_import(const std::vector<std::string>& f, bool apply);
 
 // ----------------------------------------------------------- device layout --
 // One 32-bit word per stored cell (c: its index in the population arrays):
