@@ -129,6 +129,38 @@ def test_forchheimer_parity_and_uniform_flow():
     assert np.array_equal(a.profile(0), b.profile(0))
 
 
+@pytest.mark.parametrize("nz,walls", [(3, True), (5, False), (704, True)])
+def test_size_limits_parity_with_oracle(nz, walls):
+    """The smallest columns (one fluid layer between two walls; five periodic
+    cells, one partial wavefront) and the largest (704 cells, eleven
+    wavefronts, the most LDS a workgroup takes without opting in) against the
+    oracle; one cell more than the largest is refused."""
+    say("test_size_limits_parity_with_oracle", nz, walls)
+    gray = _gray()
+    from paper_1507_06565_amd._lib import LbmError
+    G = 1e-6
+    if nz >= 64:
+        eps = smoothed_step(nz, 3).copy()
+    else:
+        eps = np.linspace(1.0, 0.5, nz)
+    if walls:
+        eps[0] = eps[-1] = 1.0
+    K = 2.0 * eps ** 3 / (1 - eps + 1e-12) ** 2
+    nue = NU / eps
+    drag = np.where(eps < 1.0, eps * NU / K, 0.0)
+    g = gray.GrayColumns(eps, nue, drag, G=(G, 0, 0), walls=walls)
+    g.run(2000)
+    ref, _ = oracle.gray_run(nz, eps, nue, drag, G=(G, 0, 0), walls=walls, nsteps=2000)
+    got = g.profile(0)
+    e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    say("rel L2", e)
+    assert e <= 1e-4
+    if nz == 704:
+        e2 = np.append(eps, 1.0)
+        with pytest.raises(LbmError):
+            gray.GrayColumns(e2, NU / e2, np.zeros(nz + 1), G=(G, 0, 0), walls=walls)
+
+
 def test_steady_state_full_column_against_oracle():
     """The closure workload's column shape (1 x 1 x 512, smoothed porosity
     step, walls) to steady state, against the FP64 oracle's steady state.
