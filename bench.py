@@ -493,14 +493,17 @@ def closure_kernels(args):
     dt = time.perf_counter() - t0
     res.update({"gray_column_nz": 512, "gray_steps_to_steady": steps, "gray_seconds": round(dt, 4),
                 "gray_us_per_step": round(dt / steps * 1e6, 3)})
+    res["gray_precision"] = 64
     ncol = 4096
-    cols = gray.GrayColumns(np.tile(eps, (ncol, 1)), np.tile(nu / eps, (ncol, 1)),
-                            np.tile(np.where(eps < 1, eps * nu / 2.0, 0.0), (ncol, 1)), G=(1e-6, 0, 0))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    cols.run(10000)
-    dt = time.perf_counter() - t0
-    res.update({"gray_columns": ncol, "gray_cell_updates_per_s": round(ncol * 512 * 10000 / dt / 1e9, 2)})
+    for bits in (64, 32):
+        cols = gray.GrayColumns(np.tile(eps, (ncol, 1)), np.tile(nu / eps, (ncol, 1)),
+                                np.tile(np.where(eps < 1, eps * nu / 2.0, 0.0), (ncol, 1)), G=(1e-6, 0, 0),
+                                precision=bits)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cols.run(10000)
+        dt = time.perf_counter() - t0
+        res.update({"gray_columns": ncol, f"gray_fp{bits}_cell_updates_per_s": round(ncol * 512 * 10000 / dt / 1e9, 2)})
     log("gray:", res)
     out = {"metric": "closure kernels: MLP TFLOP/s (BF16 MFMA) and gray-column steps/s", "value": res["forward_tflops_used"],
            "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",

@@ -62,8 +62,18 @@ lbm_status gray_set_cells(gray_ctx* ctx, const double* eps, const double* nu_eff
 lbm_status gray_set_forchheimer(gray_ctx* ctx, const double* phi);
 lbm_status gray_reset(gray_ctx* ctx);
 
-/* Advance every column exactly nsteps steps (one launch; the state stays on
- * chip, in registers and LDS, between the load and the store). */
+/* Working precision of the kernel: 64 (the default) or 32 bits.  The state
+ * is kept in FP64 between calls either way, so the precision may change
+ * between runs.  FP64 reaches the steady state of the discrete model (within
+ * 1e-10 relative of an FP64 reference); in FP32 a column stops changing once
+ * the remaining per-step updates fall below the FP32 resolution of its
+ * populations, 1e-4 to 3e-3 (relative) short of it, at 0.7 of the FP64 time
+ * per step.  Errors: LBM_E_INVAL (other values). */
+lbm_status gray_set_precision(gray_ctx* ctx, int32_t bits);
+
+/* Advance every column exactly nsteps steps (one launch; the state stays in
+ * registers and LDS, in the working precision, between the load and the
+ * store). */
 lbm_status gray_run(gray_ctx* ctx, int64_t nsteps);
 
 /* Advance every column until the FP64 sum of u_x over the column changes by

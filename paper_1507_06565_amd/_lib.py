@@ -76,6 +76,7 @@ _sig = {
     "gray_reset": ([vp], i32),
     "gray_run": ([vp, i64], i32),
     "gray_run_to_steady": ([vp, f64, i64, i64, vp], i32),
+    "gray_set_precision": ([vp, i32], i32),
     "gray_profile": ([vp, i32, vp], i32),
     "gray_destroy": ([vp], None),
     # closure network (include/mlp.h)

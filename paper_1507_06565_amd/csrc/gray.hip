@@ -21,14 +21,19 @@
 // bounce-back; the top wall may move, Ladd's correction).
 //
 // One workgroup per column, one thread per cell, the time loop inside the
-// kernel.  The nine populations with e_z = 0 never leave their cell in a
-// 1 x 1 periodic column, so they stay in registers; the ten with e_z != 0
-// pass through two LDS buffers (read one, write the other: one barrier per
-// step), each thread pulling from offsets it computes once, wall bounce-back
-// included.  Global memory is touched only to load and store the state and to
-// write the final profile.  The steady-state test (relative change of the
-// FP64 sum of u_x over check_every steps) is evaluated in the kernel with a
-// fixed-order workgroup reduction.
+// kernel.  The working precision is FP64 by default: in FP32 the column
+// stops changing 1e-4 to 3e-3 (relative) short of its steady state, once the
+// remaining per-step updates fall below the FP32 resolution of the
+// populations; FP32 is kept as an option.  Every population stays in its
+// thread's registers: the nine with e_z = 0 never leave their cell in a
+// 1 x 1 periodic column, and the ten with e_z != 0 move one cell per step
+// through LDS (every cell writes them to one of two buffers and pulls its
+// neighbours' from the other: one barrier per step; 2 x 10 x 704 x 8 bytes
+// at the largest column in FP64, which gfx950's LDS holds).  Global memory
+// is touched only to load and store the state and to write the final
+// profile.  The steady-state test (relative change of the FP64 sum of u_x
+// over check_every steps) is evaluated in the kernel with a fixed-order
+// workgroup reduction.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -42,199 +47,243 @@
 namespace lbm {
 
 struct GrayArgs {
-    float* state;         // ncols x 19 x nz
-    const float* cell;    // ncols x nz x 4: eps, omega+, omega-, D
-    const float* phi;     // ncols x nz Forchheimer coefficients, or null (all zero)
-    double* u;            // ncols x nz x 3
-    int64_t* steps;       // per column
-    double* uprev;        // per column
-    int32_t* status;      // per column: 0 running, 1 converged, -1 unstable
+    double* state;         // ncols x 19 x nz
+    const double* cell;    // ncols x nz x 4: eps, omega+, omega-, D
+    const double* phi;     // ncols x nz Forchheimer coefficients, or null (all zero)
+    double* u;             // ncols x nz x 3
+    int64_t* steps;        // per column
+    double* uprev;         // per column
+    int32_t* status;       // per column: 0 running, 1 converged, -1 unstable
     int32_t nz, walls, steady, check_every, lid;
     int64_t nsteps;
     double tol;
-    float rho0, G[3];
-    float wterm[Q];
+    double rho0, G[3];
+    double wterm[Q];
 };
 
 namespace {
 
 using L = D3Q19;
 
-// the populations with e_z != 0; slot m holds direction MOVK[m], and
-// opposite directions sit in slots m and m ^ 1
-constexpr int NMOV = 10;
-__device__ constexpr int MOVK[NMOV] = {5, 6, 11, 12, 13, 14, 15, 16, 17, 18};
+// the populations with e_z = +1 (pulled from the cell below) and, in the same
+// order, their opposites with e_z = -1 (pulled from the cell above)
+constexpr int NUP = 5;
+__host__ __device__ constexpr int upk(int i) { return i == 0 ? 5 : (i == 1 ? 11 : (i == 2 ? 14 : (i == 3 ? 15 : 18))); }
+__host__ __device__ constexpr int dnk(int i) { return opp(upk(i)); }
 
 // per-cell constants of the collision
+template <class T>
 struct GrayCell {
-    float D, phi, wp, wm, cmi, hwp, hwm, omwp, A, c45, c9, m15wp, m3cpl, den;
-    float Ge[3], hGe[3];
+    T D, phi, wp, omwp, A, c45, c9, m15wp, m3cpl, den;
+    T a1, a2;                  // g_k' = a1 g_k + a2 g_kb + ...
+    T wA_axis, wA_edge;        // w A per velocity class
+    T wmr_axis, wmr_edge;      // 3 rho0 w wm
+    T mF_axis, mF_edge;        // 3 rho0 w cmi
+    T Ge[3], hGe[3];
 };
 
-template <int BLOCK>
+// Every cell's moving populations in LDS, two buffers: slot i < NUP holds
+// direction upk(i), slot NUP + i direction dnk(i).
+template <int BLOCK, class T>
 struct GrayShared {
-    float mv[2][NMOV][BLOCK];  // moving populations, two buffers
-    double red[BLOCK / 64];    // one partial sum per wavefront
+    T mv[2][2 * NUP][BLOCK];
+    double red[BLOCK / 64];
     int stop;
 };
 
-// One pull-collide step of every active cell of the column: pull the moving
-// populations from buffer B, collide all 19 in registers, write the moving
-// post-collision values to buffer 1 - B at the cell itself.
-template <int BLOCK, bool FORCH, int B>
-__device__ __forceinline__ void gray_step(GrayShared<BLOCK>& sh, float (&g)[Q], const int (&src)[NMOV],
-                                          const float (&add)[NMOV], bool lid, const GrayCell& c, float rho_inv,
-                                          float w3r_axis, float w3r_edge, int z, float& ux, float& uy, float& uz) {
-#pragma clang fp contract(off)
+template <int BLOCK, class T>
+__device__ __forceinline__ void publish(GrayShared<BLOCK, T>& sh, int buf, const T (&g)[Q], int z) {
 #pragma unroll
-    for (int m = 0; m < NMOV; ++m) g[MOVK[m]] = (&sh.mv[B][0][0])[src[m]];
-    if (lid) {
-#pragma unroll
-        for (int m = 0; m < NMOV; ++m) g[MOVK[m]] += add[m];
+    for (int i = 0; i < NUP; ++i) {
+        sh.mv[buf][i][z] = g[upk(i)];
+        sh.mv[buf][NUP + i][z] = g[dnk(i)];
     }
-    float gp2[9], gm2[9];
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-        gp2[p] = g[2 * p + 1] + g[2 * p + 2];
-        gm2[p] = g[2 * p + 1] - g[2 * p + 2];
-    }
-    float drho = g[0], jx = 0.0f, jy = 0.0f, jz = 0.0f;
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-        const int k = 2 * p + 1;
-        drho += gp2[p];
-        if (L::ex[k] > 0) jx += gm2[p];
-        if (L::ex[k] < 0) jx -= gm2[p];
-        if (L::ey[k] > 0) jy += gm2[p];
-        if (L::ey[k] < 0) jy -= gm2[p];
-        if (L::ez[k] > 0) jz += gm2[p];
-        if (L::ez[k] < 0) jz -= gm2[p];
-    }
-    const float vx = fmaf(jx, rho_inv, c.hGe[0]), vy = fmaf(jy, rho_inv, c.hGe[1]), vz = fmaf(jz, rho_inv, c.hGe[2]);
-    float den = c.den;
-    if (FORCH && c.phi != 0.0f) {
-        const float c0 = 0.5f * (1.0f + 0.5f * c.D), c1 = 0.5f * c.phi;
-        const float vn = sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
-        den = 1.0f / (c0 + sqrtf(fmaf(c0, c0, c1 * vn)));
-    }
-    ux = vx * den;
-    uy = vy * den;
-    uz = vz * den;
-    float Fx = fmaf(-c.D, ux, c.Ge[0]), Fy = fmaf(-c.D, uy, c.Ge[1]), Fz = fmaf(-c.D, uz, c.Ge[2]);
-    const float uu = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-    if (FORCH && c.phi != 0.0f) {
-        const float pu = c.phi * sqrtf(uu);
-        Fx = fmaf(-pu, ux, Fx);
-        Fy = fmaf(-pu, uy, Fy);
-        Fz = fmaf(-pu, uz, Fz);
-    }
-    const float uF = fmaf(ux, Fx, fmaf(uy, Fy, uz * Fz));
-    // even part: dp = -wp gp + w [T0 + A (e.u (4.5 wp e.u + 9 cpl e.F) + T1)]
-    // odd part:  dm = -wm gm + 3 rho0 w (wm e.u + cmi e.F)
-    const float T0 = c.wp * drho;
-    const float T1 = fmaf(c.m15wp, uu, c.m3cpl * uF);
-    g[0] = fmaf(c.omwp, g[0], fmaf(c.A, T1, T0) * (1.0f / 3.0f));
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-        const int k = 2 * p + 1;
-        const float w = (float)weight(k);
-        const float w3r = norm2(k) == 1 ? w3r_axis : w3r_edge;
-        float eu = 0.0f, eF = 0.0f;
-        if (L::ex[k]) { eu = L::ex[k] > 0 ? ux : -ux; eF = L::ex[k] > 0 ? Fx : -Fx; }
-        if (L::ey[k]) {
-            eu = L::ex[k] ? (L::ey[k] > 0 ? eu + uy : eu - uy) : (L::ey[k] > 0 ? uy : -uy);
-            eF = L::ex[k] ? (L::ey[k] > 0 ? eF + Fy : eF - Fy) : (L::ey[k] > 0 ? Fy : -Fy);
-        }
-        if (L::ez[k]) {
-            const bool first = !L::ex[k] && !L::ey[k];
-            eu = first ? (L::ez[k] > 0 ? uz : -uz) : (L::ez[k] > 0 ? eu + uz : eu - uz);
-            eF = first ? (L::ez[k] > 0 ? Fz : -Fz) : (L::ez[k] > 0 ? eF + Fz : eF - Fz);
-        }
-        const float X = fmaf(c.c45, eu, c.c9 * eF);
-        const float Z = fmaf(c.A, fmaf(eu, X, T1), T0);
-        const float dp = fmaf(-c.hwp, gp2[p], w * Z);
-        const float dm = fmaf(-c.hwm, gm2[p], w3r * fmaf(c.wm, eu, c.cmi * eF));
-        g[k] = (g[k] + dp) + dm;
-        g[k + 1] = (g[k + 1] + dp) - dm;
-    }
-#pragma unroll
-    for (int m = 0; m < NMOV; ++m) sh.mv[1 - B][m][z] = g[MOVK[m]];
 }
 
-template <int BLOCK, bool FORCH>
+// offu / offd: where an active cell's e_z = +1 / -1 populations come from,
+// as offsets of slot 0 / NUP: the neighbour cell (periodic), or, next to a
+// wall layer, the cell's own opposite slot (half-way bounce-back)
+template <int B, int BLOCK, class T>
+__device__ __forceinline__ void pull(GrayShared<BLOCK, T>& sh, T (&g)[Q], bool active, bool walls, bool lid,
+                                     const T (&wt)[NUP], int offu, int offd, int z, int nz) {
+    if (active) {
+        const T* m = &sh.mv[B][0][0];
+        const bool top = lid && walls && z == nz - 2;
+#pragma unroll
+        for (int i = 0; i < NUP; ++i) {
+            g[upk(i)] = m[i * BLOCK + offu];
+            const T d = m[(NUP + i) * BLOCK + offd];
+            g[dnk(i)] = top ? d + wt[i] : d;
+        }
+    }
+}
+
+// One pull-collide step of the column: the pull from buffer B (plus the
+// moving-wall term at the top), the collision of the active cells, and the
+// moving post-collision values to buffer 1 - B.
+template <int BLOCK, bool FORCH, int B, class T>
+__device__ __forceinline__ void gray_step(GrayShared<BLOCK, T>& sh, T (&g)[Q], bool active, bool walls, bool lid,
+                                          const T (&wt)[NUP], int offu, int offd, const GrayCell<T>& c, T rho_inv,
+                                          int z, int nz, T& ux, T& uy, T& uz) {
+#pragma clang fp contract(off)
+    pull<B>(sh, g, active, walls, lid, wt, offu, offd, z, nz);
+    if (active) {
+        T gp2[9], gm2[9];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            gp2[p] = g[2 * p + 1] + g[2 * p + 2];
+            gm2[p] = g[2 * p + 1] - g[2 * p + 2];
+        }
+        T drho = g[0], jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int k = 2 * p + 1;
+            drho += gp2[p];
+            if (L::ex[k] > 0) jx += gm2[p];
+            if (L::ex[k] < 0) jx -= gm2[p];
+            if (L::ey[k] > 0) jy += gm2[p];
+            if (L::ey[k] < 0) jy -= gm2[p];
+            if (L::ez[k] > 0) jz += gm2[p];
+            if (L::ez[k] < 0) jz -= gm2[p];
+        }
+        const T vx = fma(jx, rho_inv, c.hGe[0]), vy = fma(jy, rho_inv, c.hGe[1]), vz = fma(jz, rho_inv, c.hGe[2]);
+        T den = c.den;
+        if (FORCH && c.phi != T(0)) {
+            const T c0 = T(0.5) * (T(1) + T(0.5) * c.D), c1 = T(0.5) * c.phi;
+            const T vn = sqrt(fma(vx, vx, fma(vy, vy, vz * vz)));
+            den = T(1) / (c0 + sqrt(fma(c0, c0, c1 * vn)));
+        }
+        ux = vx * den;
+        uy = vy * den;
+        uz = vz * den;
+        T Fx = fma(-c.D, ux, c.Ge[0]), Fy = fma(-c.D, uy, c.Ge[1]), Fz = fma(-c.D, uz, c.Ge[2]);
+        const T uu = fma(ux, ux, fma(uy, uy, uz * uz));
+        if (FORCH && c.phi != T(0)) {
+            const T pu = c.phi * sqrt(uu);
+            Fx = fma(-pu, ux, Fx);
+            Fy = fma(-pu, uy, Fy);
+            Fz = fma(-pu, uz, Fz);
+        }
+        const T uF = fma(ux, Fx, fma(uy, Fy, uz * Fz));
+        // Pair (k, kb = opp(k)) with gp = (g_k + g_kb)/2, gm = (g_k - g_kb)/2:
+        //   even part dp = -wp gp + Wp,  Wp = w [T0 + A (e.u (4.5 wp e.u + 9 cpl e.F) + T1)]
+        //   odd part  dm = -wm gm + Wm,  Wm = 3 rho0 w (wm e.u + cmi e.F)
+        //   g_k' = g_k + dp + dm = a1 g_k + a2 g_kb + (Wp + Wm)
+        //   g_kb' = g_kb + dp - dm = a1 g_kb + a2 g_k + (Wp - Wm)
+        // with a1 = 1 - wp/2 - wm/2, a2 = wm/2 - wp/2; the weights w and
+        // 3 rho0 w are folded into per-class (axis / edge) constants.
+        const T T0 = c.wp * drho;
+        const T T1 = fma(c.m15wp, uu, c.m3cpl * uF);
+        g[0] = fma(c.omwp, g[0], fma(c.A, T1, T0) * T(1.0 / 3.0));
+        const T H[3] = {c.c9 * Fx, c.c9 * Fy, c.c9 * Fz};                   // 9 cpl F
+        const T Ma[3] = {c.mF_axis * Fx, c.mF_axis * Fy, c.mF_axis * Fz};   // 3 rho0 w cmi F, axis
+        const T Me[3] = {c.mF_edge * Fx, c.mF_edge * Fy, c.mF_edge * Fz};   // same, edge
+        const T wT0_axis = T(1.0 / 18.0) * T0, wT0_edge = T(1.0 / 36.0) * T0;
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            const int k = 2 * p + 1;
+            const bool axis = norm2(k) == 1;
+            const int e[3] = {L::ex[k], L::ey[k], L::ez[k]};
+            const T uc[3] = {ux, uy, uz};
+            // e.u, 9 cpl e.F and 3 rho0 w cmi e.F as signed sums of the nonzero components
+            T eu = T(0), hF = T(0), mF = T(0);
+            bool first = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (e[d] == 0) continue;
+                if (first) {
+                    eu = e[d] > 0 ? uc[d] : -uc[d];
+                    hF = e[d] > 0 ? H[d] : -H[d];
+                    mF = e[d] > 0 ? (axis ? Ma[d] : Me[d]) : -(axis ? Ma[d] : Me[d]);
+                    first = false;
+                } else {
+                    eu = e[d] > 0 ? eu + uc[d] : eu - uc[d];
+                    hF = e[d] > 0 ? hF + H[d] : hF - H[d];
+                    mF = e[d] > 0 ? mF + (axis ? Ma[d] : Me[d]) : mF - (axis ? Ma[d] : Me[d]);
+                }
+            }
+            const T X = fma(c.c45, eu, hF);
+            const T Wp = fma(axis ? c.wA_axis : c.wA_edge, fma(eu, X, T1), axis ? wT0_axis : wT0_edge);
+            const T Wm = fma(axis ? c.wmr_axis : c.wmr_edge, eu, mF);
+            const T S = Wp + Wm, Dd = Wp - Wm;
+            const T gk = g[k], gb = g[k + 1];
+            g[k] = fma(c.a1, gk, fma(c.a2, gb, S));
+            g[k + 1] = fma(c.a1, gb, fma(c.a2, gk, Dd));
+        }
+    }
+    publish(sh, 1 - B, g, z);
+}
+
+template <int BLOCK, bool FORCH, class T>
 __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
 #pragma clang fp contract(off)
-    __shared__ GrayShared<BLOCK> sh;
+    __shared__ GrayShared<BLOCK, T> sh;
     const int col = blockIdx.x;
     const int z = threadIdx.x;
     const int nz = a.nz;
     const bool live = z < nz;
-    const bool active = live && !(a.walls && (z == 0 || z == nz - 1));
-    float* gs = a.state + (int64_t)col * Q * nz;
-    float g[Q];
-    GrayCell c{};
+    const bool walls = a.walls != 0;
+    const bool active = live && !(walls && (z == 0 || z == nz - 1));
+    double* gs = a.state + (int64_t)col * Q * nz;
+    T g[Q];
+    GrayCell<T> c{};
     {
-        float eps = 1.0f, wp = 1.0f, wm = 1.0f, D = 0.0f;
+        double eps = 1.0, wp = 1.0, wm = 1.0, D = 0.0;
         if (live) {
-            const float* cp = a.cell + ((int64_t)col * nz + z) * 4;
+            const double* cp = a.cell + ((int64_t)col * nz + z) * 4;
             eps = cp[0]; wp = cp[1]; wm = cp[2]; D = cp[3];
-            if (FORCH) c.phi = a.phi[(int64_t)col * nz + z];
+            if (FORCH) c.phi = T(a.phi[(int64_t)col * nz + z]);
         }
 #pragma unroll
-        for (int k = 0; k < Q; ++k) g[k] = live ? gs[k * nz + z] : 0.0f;
-        const float cpl = 1.0f - 0.5f * wp;
-        c.D = D;
-        c.wp = wp;
-        c.wm = wm;
-        c.cmi = 1.0f - 0.5f * wm;
-        c.hwp = 0.5f * wp;
-        c.hwm = 0.5f * wm;
-        c.omwp = 1.0f - wp;
-        c.A = a.rho0 * (1.0f / eps);
-        c.c45 = 4.5f * wp;
-        c.c9 = 9.0f * cpl;
-        c.m15wp = -1.5f * wp;
-        c.m3cpl = -3.0f * cpl;
-        c.den = 1.0f / (1.0f + 0.5f * D);
+        for (int k = 0; k < Q; ++k) g[k] = live ? T(gs[k * nz + z]) : T(0);
+        // constants formed in FP64, then rounded once to the working precision
+        const double cpl = 1.0 - 0.5 * wp, cmi = 1.0 - 0.5 * wm;
+        const double hwp = 0.5 * wp, hwm = 0.5 * wm;
+        const double r3a = 3.0 * a.rho0 * (1.0 / 18.0), r3e = 3.0 * a.rho0 * (1.0 / 36.0);
+        const double A = a.rho0 * (1.0 / eps);
+        c.D = T(D);
+        c.wp = T(wp);
+        c.omwp = T(1.0 - wp);
+        c.A = T(A);
+        c.c45 = T(4.5 * wp);
+        c.c9 = T(9.0 * cpl);
+        c.m15wp = T(-1.5 * wp);
+        c.m3cpl = T(-3.0 * cpl);
+        c.den = T(1.0 / (1.0 + 0.5 * D));
+        c.a1 = T((1.0 - hwp) - hwm);
+        c.a2 = T(hwm - hwp);
+        c.wA_axis = T((1.0 / 18.0) * A);
+        c.wA_edge = T((1.0 / 36.0) * A);
+        c.wmr_axis = T(r3a * wm);
+        c.wmr_edge = T(r3e * wm);
+        c.mF_axis = T(r3a * cmi);
+        c.mF_edge = T(r3e * cmi);
         for (int i = 0; i < 3; ++i) {
-            c.Ge[i] = eps * a.G[i];
-            c.hGe[i] = 0.5f * c.Ge[i];
+            c.Ge[i] = T(eps * a.G[i]);
+            c.hGe[i] = T(0.5 * eps * a.G[i]);
         }
     }
-    // pull sources of the moving populations: the neighbour cell (periodic
-    // in z), or this cell's opposite population where the neighbour is a wall
-    // layer (half-way bounce-back, plus the moving-wall term at the top)
-    int src[NMOV];
-    float add[NMOV];
+    T wt[NUP];
 #pragma unroll
-    for (int m = 0; m < NMOV; ++m) {
-        const int k = MOVK[m];
-        int zs = z - L::ez[k];
-        add[m] = 0.0f;
-        if (!active) {
-            src[m] = m * BLOCK + z;
-        } else if (a.walls && (zs == 0 || zs == nz - 1)) {
-            src[m] = (m ^ 1) * BLOCK + z;
-            if (zs == nz - 1) add[m] = a.wterm[k];
-        } else {
-            zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
-            src[m] = m * BLOCK + zs;
-        }
-        sh.mv[0][m][z] = g[k];
-    }
+    for (int i = 0; i < NUP; ++i) wt[i] = T(a.wterm[dnk(i)]);
     const bool lid = a.lid != 0;
-    const float rho_inv = 1.0f / a.rho0;
-    const float w3r_axis = 3.0f * a.rho0 * (float)(1.0 / 18.0), w3r_edge = 3.0f * a.rho0 * (float)(1.0 / 36.0);
-    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+    int offu = z - 1, offd = z + 1;
+    if (walls && offu == 0) offu = NUP * BLOCK + z;
+    else if (offu < 0) offu += nz;
+    if (walls && offd == nz - 1) offd = z - NUP * BLOCK;
+    else if (offd >= nz) offd -= nz;
+    const T rho_inv = T(1.0 / a.rho0);
+    T ux = T(0), uy = T(0), uz = T(0);
     const int64_t s0 = a.steps[col];
     int64_t s = s0;
     int until_check = a.check_every;
     bool stop = a.nsteps <= 0 || (a.steady && a.status[col] != 0);
+    publish(sh, 0, g, z);
     __syncthreads();
-    // after each step: the barrier that orders this step's writes before the
-    // next step's reads, and, every check_every steps, the steady-state test
-    // on the FP64 sum of u_x (per-wavefront butterflies, then the wavefront
-    // sums in order)
+    // after each step: the barrier that orders this step's boundary values
+    // before the next step's reads, and, every check_every steps, the
+    // steady-state test on the FP64 sum of u_x (per-wavefront butterflies,
+    // then the wavefront sums in order)
     auto finish = [&]() {
         ++s;
         stop = s - s0 >= a.nsteps;
@@ -263,18 +312,18 @@ __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
         }
     };
     while (!stop) {
-        if (active) gray_step<BLOCK, FORCH, 0>(sh, g, src, add, lid, c, rho_inv, w3r_axis, w3r_edge, z, ux, uy, uz);
+        gray_step<BLOCK, FORCH, 0, T>(sh, g, active, walls, lid, wt, offu, offd, c, rho_inv, z, nz, ux, uy, uz);
         finish();
         if (stop) break;
-        if (active) gray_step<BLOCK, FORCH, 1>(sh, g, src, add, lid, c, rho_inv, w3r_axis, w3r_edge, z, ux, uy, uz);
+        gray_step<BLOCK, FORCH, 1, T>(sh, g, active, walls, lid, wt, offu, offd, c, rho_inv, z, nz, ux, uy, uz);
         finish();
     }
     // every thread holds its own cell's post-collision populations
     if (live) {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) gs[k * nz + z] = g[k];
+        for (int k = 0; k < Q; ++k) gs[k * nz + z] = (double)g[k];
         double* uo = a.u + ((int64_t)col * nz + z) * 3;
-        uo[0] = ux; uo[1] = uy; uo[2] = uz;
+        uo[0] = (double)ux; uo[1] = (double)uy; uo[2] = (double)uz;
     }
     if (z == 0) a.steps[col] = s;
 }
@@ -293,6 +342,7 @@ struct gray_ctx {
     int64_t off_state = 0, off_cell = 0, off_phi = 0, off_u = 0, off_steps = 0, off_uprev = 0, off_status = 0;
     GrayArgs args{};
     double lambda = 3.0 / 16.0, rho0 = 1.0;
+    int precision = 64;  // working precision of the kernel, 64 or 32 bits
     std::vector<int64_t> steps;
 };
 
@@ -305,9 +355,9 @@ struct GPlan {
 GPlan gplan(int ncols, int nz) {
     GPlan P{};
     int64_t o = 0;
-    P.state = o; o = align_up(o + (int64_t)ncols * Q * nz * 4, 256);
-    P.cell = o; o = align_up(o + (int64_t)ncols * nz * 16, 256);
-    P.phi = o; o = align_up(o + (int64_t)ncols * nz * 4, 256);
+    P.state = o; o = align_up(o + (int64_t)ncols * Q * nz * 8, 256);
+    P.cell = o; o = align_up(o + (int64_t)ncols * nz * 32, 256);
+    P.phi = o; o = align_up(o + (int64_t)ncols * nz * 8, 256);
     P.u = o; o = align_up(o + (int64_t)ncols * nz * 24, 256);
     P.steps = o; o = align_up(o + (int64_t)ncols * 8, 256);
     P.uprev = o; o = align_up(o + (int64_t)ncols * 8, 256);
@@ -324,7 +374,7 @@ GPlan gplan(int ncols, int nz) {
 
 lbm_status upload_cells(gray_ctx* c, const double* eps, const double* nu_eff, const double* drag) {
     const int64_t n = (int64_t)c->ncols * c->nz;
-    std::vector<float> cell((size_t)n * 4);
+    std::vector<double> cell((size_t)n * 4);
     for (int64_t i = 0; i < n; ++i) {
         if (!(eps[i] > 0.0 && eps[i] <= 1.0)) return set_error(LBM_E_INVAL, "porosity must lie in (0, 1]");
         if (!(nu_eff[i] > 0.0) || !std::isfinite(nu_eff[i])) return set_error(LBM_E_INVAL, "nu_eff must be positive");
@@ -333,12 +383,12 @@ lbm_status upload_cells(gray_ctx* c, const double* eps, const double* nu_eff, co
         const double tm = 0.5 + c->lambda / (tp - 0.5);
         const double wp = 1.0 / tp, wm = 1.0 / tm;
         if (!(wm > 0.0 && wm < 2.0)) return set_error(LBM_E_INVAL, "omega- outside (0, 2)");
-        cell[4 * i + 0] = (float)eps[i];
-        cell[4 * i + 1] = (float)wp;
-        cell[4 * i + 2] = (float)wm;
-        cell[4 * i + 3] = (float)drag[i];
+        cell[4 * i + 0] = eps[i];
+        cell[4 * i + 1] = wp;
+        cell[4 * i + 2] = wm;
+        cell[4 * i + 3] = drag[i];
     }
-    GCHK(hipMemcpyAsync(c->buf + c->off_cell, cell.data(), cell.size() * 4, hipMemcpyHostToDevice, c->stream),
+    GCHK(hipMemcpyAsync(c->buf + c->off_cell, cell.data(), cell.size() * 8, hipMemcpyHostToDevice, c->stream),
          "upload cell parameters");
     GCHK(hipStreamSynchronize(c->stream), "synchronise");
     return LBM_OK;
@@ -347,12 +397,15 @@ lbm_status upload_cells(gray_ctx* c, const double* eps, const double* nu_eff, co
 lbm_status launch(gray_ctx* c) {
     const int block = (int)align_up(c->nz, 64);
     const bool forch = c->args.phi != nullptr;
+    const bool fp64 = c->precision == 64;
     hipError_t e;
     switch (block) {
-#define GB(B)                                                                       \
-    case B:                                                                         \
-        if (forch) k_gray<B, true><<<c->ncols, B, 0, c->stream>>>(c->args);         \
-        else k_gray<B, false><<<c->ncols, B, 0, c->stream>>>(c->args);              \
+#define GB(B)                                                                                 \
+    case B:                                                                                   \
+        if (fp64 && forch) k_gray<B, true, double><<<c->ncols, B, 0, c->stream>>>(c->args);   \
+        else if (fp64) k_gray<B, false, double><<<c->ncols, B, 0, c->stream>>>(c->args);      \
+        else if (forch) k_gray<B, true, float><<<c->ncols, B, 0, c->stream>>>(c->args);       \
+        else k_gray<B, false, float><<<c->ncols, B, 0, c->stream>>>(c->args);                 \
         break;
         GB(64) GB(128) GB(192) GB(256) GB(320) GB(384) GB(448) GB(512) GB(576) GB(640) GB(704)
 #undef GB
@@ -372,9 +425,8 @@ lbm_status launch(gray_ctx* c) {
 extern "C" {
 
 lbm_status gray_required_bytes(int32_t ncols, int32_t nz, int64_t* bytes) {
-    // two buffers of the ten moving populations (80 B per cell, nz rounded up
-    // to a multiple of 64) and the reduction buffer must fit the 64 KB of LDS
-    // a workgroup gets without opting in to more
+    // the column is one workgroup of nz rounded up to a multiple of 64
+    // threads, at most 704 (eleven wavefronts, three per SIMD)
     if (ncols < 1 || nz < 3 || nz > 704 || !bytes) return set_error(LBM_E_INVAL, "need ncols >= 1 and 3 <= nz <= 704");
     *bytes = gplan(ncols, nz).total;
     return LBM_OK;
@@ -401,19 +453,19 @@ lbm_status gray_init(int32_t ncols, int32_t nz, int32_t walls, const double* eps
     c->off_phi = P.phi;
     GrayArgs& a = c->args;
     a.phi = nullptr;
-    a.state = reinterpret_cast<float*>(c->buf + P.state);
-    a.cell = reinterpret_cast<const float*>(c->buf + P.cell);
+    a.state = reinterpret_cast<double*>(c->buf + P.state);
+    a.cell = reinterpret_cast<const double*>(c->buf + P.cell);
     a.u = reinterpret_cast<double*>(c->buf + P.u);
     a.steps = reinterpret_cast<int64_t*>(c->buf + P.steps);
     a.uprev = reinterpret_cast<double*>(c->buf + P.uprev);
     a.status = reinterpret_cast<int32_t*>(c->buf + P.status);
     a.nz = nz; a.walls = c->walls;
-    a.rho0 = (float)rho0;
-    for (int i = 0; i < 3; ++i) a.G[i] = (float)G[i];
+    a.rho0 = rho0;
+    for (int i = 0; i < 3; ++i) a.G[i] = G[i];
     const double zero[3] = {0, 0, 0};
     const double* lw = lid ? lid : zero;
     for (int k = 0; k < Q; ++k)
-        a.wterm[k] = (float)(6.0 * weight(k) * rho0 * (D3Q19::ex[k] * lw[0] + D3Q19::ey[k] * lw[1] + D3Q19::ez[k] * lw[2]));
+        a.wterm[k] = 6.0 * weight(k) * rho0 * (D3Q19::ex[k] * lw[0] + D3Q19::ey[k] * lw[1] + D3Q19::ez[k] * lw[2]);
     a.lid = (lw[0] != 0.0 || lw[1] != 0.0 || lw[2] != 0.0) ? 1 : 0;
     s = upload_cells(c, eps, nu_eff, drag);
     if (s == LBM_OK) s = gray_reset(c);
@@ -425,7 +477,7 @@ lbm_status gray_init(int32_t ncols, int32_t nz, int32_t walls, const double* eps
 lbm_status gray_reset(gray_ctx* c) {
     if (!c) return set_error(LBM_E_INVAL, "null context");
     std::vector<double> nanv(c->ncols, NAN);
-    GCHK(hipMemsetAsync(c->buf + c->off_state, 0, (size_t)c->ncols * Q * c->nz * 4, c->stream), "zero state");
+    GCHK(hipMemsetAsync(c->buf + c->off_state, 0, (size_t)c->ncols * Q * c->nz * 8, c->stream), "zero state");
     GCHK(hipMemsetAsync(c->buf + c->off_u, 0, (size_t)c->ncols * c->nz * 24, c->stream), "zero profile");
     GCHK(hipMemsetAsync(c->buf + c->off_steps, 0, (size_t)c->ncols * 8, c->stream), "zero steps");
     GCHK(hipMemsetAsync(c->buf + c->off_status, 0, (size_t)c->ncols * 4, c->stream), "zero status");
@@ -447,15 +499,15 @@ lbm_status gray_set_forchheimer(gray_ctx* c, const double* phi) {
         return LBM_OK;
     }
     const int64_t n = (int64_t)c->ncols * c->nz;
-    std::vector<float> f((size_t)n);
+    std::vector<double> f((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
         if (!(phi[i] >= 0.0) || !std::isfinite(phi[i])) return set_error(LBM_E_INVAL, "Forchheimer coefficients must be >= 0");
-        f[i] = (float)phi[i];
+        f[i] = phi[i];
     }
-    GCHK(hipMemcpyAsync(c->buf + c->off_phi, f.data(), f.size() * 4, hipMemcpyHostToDevice, c->stream),
+    GCHK(hipMemcpyAsync(c->buf + c->off_phi, f.data(), f.size() * 8, hipMemcpyHostToDevice, c->stream),
          "upload Forchheimer coefficients");
     GCHK(hipStreamSynchronize(c->stream), "synchronise");
-    c->args.phi = reinterpret_cast<const float*>(c->buf + c->off_phi);
+    c->args.phi = reinterpret_cast<const double*>(c->buf + c->off_phi);
     return LBM_OK;
 }
 
@@ -484,6 +536,12 @@ lbm_status gray_run_to_steady(gray_ctx* c, double rel_tol, int64_t check_every, 
     GCHK(hipStreamSynchronize(c->stream), "synchronise");
     for (int i = 0; i < c->ncols; ++i)
         if (st[i] < 0) return set_error(LBM_E_UNSTABLE, "gray column " + std::to_string(i) + " became unstable");
+    return LBM_OK;
+}
+
+lbm_status gray_set_precision(gray_ctx* c, int32_t bits) {
+    if (!c || (bits != 32 && bits != 64)) return set_error(LBM_E_INVAL, "precision must be 32 or 64 bits");
+    c->precision = bits;
     return LBM_OK;
 }
 

@@ -21,7 +21,7 @@ class GrayColumns:
     """ncols independent 1 x 1 x nz columns; eps, nu_eff, drag: (ncols, nz)."""
 
     def __init__(self, eps, nu_eff, drag, G=(0.0, 0.0, 0.0), walls=True, lid=None, magic_lambda=3.0 / 16.0,
-                 rho0=1.0, device="cuda", stream=None):
+                 rho0=1.0, device="cuda", stream=None, precision=64):
         eps = np.atleast_2d(np.asarray(eps, dtype=np.float64))
         self.ncols, self.nz = eps.shape
         self._eps = _arr(eps, self.ncols, self.nz)
@@ -39,6 +39,12 @@ class GrayColumns:
                             None if lw is None else lw.ctypes.data, C.c_void_p(self.buf.data_ptr()), nb.value,
                             C.c_void_p(self.stream.cuda_stream), C.byref(ptr)), "gray_init")
         self.ptr = ptr
+        if precision != 64:
+            self.set_precision(precision)
+
+    def set_precision(self, bits):
+        """Working precision of the kernel, 64 (default) or 32 bits (gray_set_precision)."""
+        check(lib.gray_set_precision(self.ptr, int(bits)), "gray_set_precision")
 
     def __del__(self, _destroy=lib.gray_destroy):
         if getattr(self, "ptr", None):
