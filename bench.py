@@ -549,7 +549,7 @@ def main():
                          "instead of the run to steady state")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the z-slab decomposition is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "rev-batch":

@@ -34,7 +34,7 @@ def test_learned_closure_gains_over_reference_model():
 
 
 @pytest.mark.timeout(600)
-def test_learned_closure_north_star_at_bed_shape():
+def test_learned_closure_criterion_at_bed_shape():
     """The closure's target at the coupled-flow bed shape (128 x 64 x 256
     beds, radii U[6,10], bed layers [1,128), the default experiment: nine
     training beds, three held-out beds of porosities and packings never
