@@ -75,7 +75,7 @@ __host__ __device__ constexpr int dnk(int i) { return opp(upk(i)); }
 template <class T>
 struct GrayCell {
     T D, phi, wp, omwp, A, c45, c9, m15wp, m3cpl, den;
-    T a1, a2;                  // g_k' = a1 g_k + a2 g_kb + ...
+    T hp, hm;                  // (1 - omega+)/2, (1 - omega-)/2
     T wA_axis, wA_edge;        // w A per velocity class
     T wmr_axis, wmr_edge;      // 3 rho0 w wm
     T mF_axis, mF_edge;        // 3 rho0 w cmi
@@ -134,18 +134,24 @@ __device__ __forceinline__ void gray_step(GrayShared<BLOCK, T>& sh, T (&g)[Q], b
             gp2[p] = g[2 * p + 1] + g[2 * p + 2];
             gm2[p] = g[2 * p + 1] - g[2 * p + 2];
         }
-        T drho = g[0], jx = T(0), jy = T(0), jz = T(0);
+        // momentum: signed sums of the gm2 terms, each started from its
+        // first term rather than from zero
+        T drho = g[0], j[3] = {T(0), T(0), T(0)};
+        bool started[3] = {false, false, false};
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
             const int k = 2 * p + 1;
             drho += gp2[p];
-            if (L::ex[k] > 0) jx += gm2[p];
-            if (L::ex[k] < 0) jx -= gm2[p];
-            if (L::ey[k] > 0) jy += gm2[p];
-            if (L::ey[k] < 0) jy -= gm2[p];
-            if (L::ez[k] > 0) jz += gm2[p];
-            if (L::ez[k] < 0) jz -= gm2[p];
+            const int e[3] = {L::ex[k], L::ey[k], L::ez[k]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (e[d] == 0) continue;
+                if (!started[d]) j[d] = e[d] > 0 ? gm2[p] : -gm2[p];
+                else j[d] = e[d] > 0 ? j[d] + gm2[p] : j[d] - gm2[p];
+                started[d] = true;
+            }
         }
+        const T jx = j[0], jy = j[1], jz = j[2];
         const T vx = fma(jx, rho_inv, c.hGe[0]), vy = fma(jy, rho_inv, c.hGe[1]), vz = fma(jz, rho_inv, c.hGe[2]);
         T den = c.den;
         if (FORCH && c.phi != T(0)) {
@@ -168,10 +174,11 @@ __device__ __forceinline__ void gray_step(GrayShared<BLOCK, T>& sh, T (&g)[Q], b
         // Pair (k, kb = opp(k)) with gp = (g_k + g_kb)/2, gm = (g_k - g_kb)/2:
         //   even part dp = -wp gp + Wp,  Wp = w [T0 + A (e.u (4.5 wp e.u + 9 cpl e.F) + T1)]
         //   odd part  dm = -wm gm + Wm,  Wm = 3 rho0 w (wm e.u + cmi e.F)
-        //   g_k' = g_k + dp + dm = a1 g_k + a2 g_kb + (Wp + Wm)
-        //   g_kb' = g_kb + dp - dm = a1 g_kb + a2 g_k + (Wp - Wm)
-        // with a1 = 1 - wp/2 - wm/2, a2 = wm/2 - wp/2; the weights w and
-        // 3 rho0 w are folded into per-class (axis / edge) constants.
+        //   g_k'  = (gp + dp) + (gm + dm) = P + M
+        //   g_kb' = (gp + dp) - (gm + dm) = P - M
+        // with P = hp gp2 + Wp, M = hm gm2 + Wm, gp2 = 2 gp, gm2 = 2 gm,
+        // hp = (1 - wp)/2, hm = (1 - wm)/2; the weights w and 3 rho0 w are
+        // folded into per-class (axis / edge) constants.
         const T T0 = c.wp * drho;
         const T T1 = fma(c.m15wp, uu, c.m3cpl * uF);
         g[0] = fma(c.omwp, g[0], fma(c.A, T1, T0) * T(1.0 / 3.0));
@@ -205,10 +212,9 @@ __device__ __forceinline__ void gray_step(GrayShared<BLOCK, T>& sh, T (&g)[Q], b
             const T X = fma(c.c45, eu, hF);
             const T Wp = fma(axis ? c.wA_axis : c.wA_edge, fma(eu, X, T1), axis ? wT0_axis : wT0_edge);
             const T Wm = fma(axis ? c.wmr_axis : c.wmr_edge, eu, mF);
-            const T S = Wp + Wm, Dd = Wp - Wm;
-            const T gk = g[k], gb = g[k + 1];
-            g[k] = fma(c.a1, gk, fma(c.a2, gb, S));
-            g[k + 1] = fma(c.a1, gb, fma(c.a2, gk, Dd));
+            const T P = fma(c.hp, gp2[p], Wp), M = fma(c.hm, gm2[p], Wm);
+            g[k] = P + M;
+            g[k + 1] = P - M;
         }
     }
     publish(sh, 1 - B, g, z);
@@ -238,7 +244,6 @@ __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
         for (int k = 0; k < Q; ++k) g[k] = live ? T(gs[k * nz + z]) : T(0);
         // constants formed in FP64, then rounded once to the working precision
         const double cpl = 1.0 - 0.5 * wp, cmi = 1.0 - 0.5 * wm;
-        const double hwp = 0.5 * wp, hwm = 0.5 * wm;
         const double r3a = 3.0 * a.rho0 * (1.0 / 18.0), r3e = 3.0 * a.rho0 * (1.0 / 36.0);
         const double A = a.rho0 * (1.0 / eps);
         c.D = T(D);
@@ -250,8 +255,8 @@ __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
         c.m15wp = T(-1.5 * wp);
         c.m3cpl = T(-3.0 * cpl);
         c.den = T(1.0 / (1.0 + 0.5 * D));
-        c.a1 = T((1.0 - hwp) - hwm);
-        c.a2 = T(hwm - hwp);
+        c.hp = T(0.5 * (1.0 - wp));
+        c.hm = T(0.5 * (1.0 - wm));
         c.wA_axis = T((1.0 / 18.0) * A);
         c.wA_edge = T((1.0 / 36.0) * A);
         c.wmr_axis = T(r3a * wm);
