@@ -67,8 +67,8 @@ lbm_status gray_reset(gray_ctx* ctx);
  * between runs.  FP64 reaches the steady state of the discrete model (within
  * 1e-10 relative of an FP64 reference); in FP32 a column stops changing once
  * the remaining per-step updates fall below the FP32 resolution of its
- * populations, 1e-4 to 3e-3 (relative) short of it, at 0.7 of the FP64 time
- * per step.  Errors: LBM_E_INVAL (other values). */
+ * populations, 1e-4 to 3e-3 (relative) short of it, at 0.7-0.9 of the FP64
+ * time per step.  Errors: LBM_E_INVAL (other values). */
 lbm_status gray_set_precision(gray_ctx* ctx, int32_t bits);
 
 /* Advance every column exactly nsteps steps (one launch; the state stays in
