@@ -104,16 +104,21 @@ __device__ __forceinline__ void publish(GrayShared<BLOCK, T>& sh, int buf, const
 // as offsets of slot 0 / NUP: the neighbour cell (periodic), or, next to a
 // wall layer, the cell's own opposite slot (half-way bounce-back)
 template <int B, int BLOCK, class T>
-__device__ __forceinline__ void pull(GrayShared<BLOCK, T>& sh, T (&g)[Q], bool active, bool walls, bool lid,
-                                     const T (&wt)[NUP], int offu, int offd, int z, int nz) {
+__device__ __forceinline__ void pull(GrayShared<BLOCK, T>& sh, T (&g)[Q], bool active, bool lid, const T (&wt)[NUP],
+                                     int offu, int offd) {
     if (active) {
         const T* m = &sh.mv[B][0][0];
-        const bool top = lid && walls && z == nz - 2;
 #pragma unroll
         for (int i = 0; i < NUP; ++i) {
             g[upk(i)] = m[i * BLOCK + offu];
-            const T d = m[(NUP + i) * BLOCK + offd];
-            g[dnk(i)] = top ? d + wt[i] : d;
+            g[dnk(i)] = m[(NUP + i) * BLOCK + offd];
+        }
+        // the moving-wall term (zero but in the cell below the top wall);
+        // lid is uniform over the launch, so the branch costs nothing
+        // without a moving wall
+        if (lid) {
+#pragma unroll
+            for (int i = 0; i < NUP; ++i) g[dnk(i)] += wt[i];
         }
     }
 }
@@ -122,11 +127,11 @@ __device__ __forceinline__ void pull(GrayShared<BLOCK, T>& sh, T (&g)[Q], bool a
 // moving-wall term at the top), the collision of the active cells, and the
 // moving post-collision values to buffer 1 - B.
 template <int BLOCK, bool FORCH, int B, class T>
-__device__ __forceinline__ void gray_step(GrayShared<BLOCK, T>& sh, T (&g)[Q], bool active, bool walls, bool lid,
+__device__ __forceinline__ void gray_step(GrayShared<BLOCK, T>& sh, T (&g)[Q], bool active, bool lid,
                                           const T (&wt)[NUP], int offu, int offd, const GrayCell<T>& c, T rho_inv,
-                                          int z, int nz, T& ux, T& uy, T& uz) {
+                                          int z, T& ux, T& uy, T& uz) {
 #pragma clang fp contract(off)
-    pull<B>(sh, g, active, walls, lid, wt, offu, offd, z, nz);
+    pull<B>(sh, g, active, lid, wt, offu, offd);
     if (active) {
         T gp2[9], gm2[9];
 #pragma unroll
@@ -268,10 +273,13 @@ __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
             c.hGe[i] = T(0.5 * eps * a.G[i]);
         }
     }
-    T wt[NUP];
-#pragma unroll
-    for (int i = 0; i < NUP; ++i) wt[i] = T(a.wterm[dnk(i)]);
     const bool lid = a.lid != 0;
+    // the moving-wall term of the populations pulled from the top wall, in
+    // the cell below it only
+    T wt[NUP];
+    const bool top = lid && walls && z == nz - 2;
+#pragma unroll
+    for (int i = 0; i < NUP; ++i) wt[i] = top ? T(a.wterm[dnk(i)]) : T(0);
     int offu = z - 1, offd = z + 1;
     if (walls && offu == 0) offu = NUP * BLOCK + z;
     else if (offu < 0) offu += nz;
@@ -317,10 +325,10 @@ __global__ void __launch_bounds__(BLOCK) k_gray(GrayArgs a) {
         }
     };
     while (!stop) {
-        gray_step<BLOCK, FORCH, 0, T>(sh, g, active, walls, lid, wt, offu, offd, c, rho_inv, z, nz, ux, uy, uz);
+        gray_step<BLOCK, FORCH, 0, T>(sh, g, active, lid, wt, offu, offd, c, rho_inv, z, ux, uy, uz);
         finish();
         if (stop) break;
-        gray_step<BLOCK, FORCH, 1, T>(sh, g, active, walls, lid, wt, offu, offd, c, rho_inv, z, nz, ux, uy, uz);
+        gray_step<BLOCK, FORCH, 1, T>(sh, g, active, lid, wt, offu, offd, c, rho_inv, z, ux, uy, uz);
         finish();
     }
     // every thread holds its own cell's post-collision populations
