@@ -200,3 +200,30 @@ def test_steady_state_full_column_against_oracle(precision):
         say("precision", precision, "scale", s_, "steps", steps, "oracle steps (scale 8)", nref,
             "max rel diff vs FP64", d)
         assert d < bound
+
+
+def test_precision_switch_between_runs():
+    """The state is kept in FP64 between calls, so a run may continue in the
+    other working precision: 1000 steps in FP32 then 1000 in FP64 stay
+    within the FP32 tolerance of the oracle's 2000 steps; precisions other
+    than 32 and 64 bits are refused."""
+    say("test_precision_switch_between_runs")
+    gray = _gray()
+    from paper_1507_06565_amd._lib import LbmError
+    nz = 130
+    eps = smoothed_step(nz, 5).copy()
+    eps[0] = eps[-1] = 1.0
+    K = 2.0 * eps ** 3 / (1 - eps + 1e-12) ** 2
+    nue = NU / eps
+    drag = np.where(eps < 1.0, eps * NU / K, 0.0)
+    g = gray.GrayColumns(eps, nue, drag, G=(1e-6, 0, 0), walls=True, precision=32)
+    g.run(1000)
+    g.set_precision(64)
+    g.run(1000)
+    ref, _ = oracle.gray_run(nz, eps, nue, drag, G=(1e-6, 0, 0), walls=True, nsteps=2000)
+    e = np.linalg.norm(g.profile(0) - ref) / np.linalg.norm(ref)
+    say("rel L2", e)
+    assert e <= 1e-4
+    for bits in (16, 0, 128):
+        with pytest.raises(LbmError):
+            g.set_precision(bits)
