@@ -62,7 +62,8 @@ lbm_status gray_set_cells(gray_ctx* ctx, const double* eps, const double* nu_eff
 lbm_status gray_set_forchheimer(gray_ctx* ctx, const double* phi);
 lbm_status gray_reset(gray_ctx* ctx);
 
-/* Working precision of the kernel: 64 (the default) or 32 bits.  The state
+/* Working precision in which the kernel steps the Sec. 4 model (the paper
+ * fixes none): 64 (the default) or 32 bits.  The state
  * is kept in FP64 between calls either way, so the precision may change
  * between runs.  FP64 reaches the steady state of the discrete model (within
  * 1e-10 relative of an FP64 reference); in FP32 a column stops changing once
