@@ -311,15 +311,19 @@ __device__ __forceinline__ float cell_update(PA pa, PA pb, CellHead h, const flo
     //    step plus c0 times the second node's value
     if (mask) {
         // every coefficient and partial-value load is issued before any is
-        // used, without branches: for a direction that is not a link the rank
-        // points at a neighbouring record (the arrays are padded), whose value
-        // is unused
+        // used, each only by the lanes that have that link: a wavefront skips
+        // the directions none of its lanes links along, and a load serves
+        // only the lanes that need its value
 #pragma unroll
         for (int k = 1; k < Q; ++k) {
             const int kk = opp(k);
-            const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
-            prm[k] = *(const __attribute__((address_space(1))) float*)(lp + (li << 2));
-            pv[k] = *(const __attribute__((address_space(1))) float*)(vp + (li << 2));
+            prm[k] = 0.0f;
+            pv[k] = 0.0f;
+            if (mask & (1u << (kk - 1))) {
+                const uint32_t li = (uint32_t)base + __popc(mask & ((1u << (kk - 1)) - 1u));
+                prm[k] = *(const __attribute__((address_space(1))) float*)(lp + (li << 2));
+                pv[k] = *(const __attribute__((address_space(1))) float*)(vp + (li << 2));
+            }
         }
         // in place: g[kk] is read only when c0 != 0, i.e. when x + e_k is
         // fluid, so (x, k) is not itself a link and g[kk] is its pulled value
